@@ -1,0 +1,131 @@
+"""Seeded synthetic inputs: grid cut problems (unaries w, edge weights a).
+
+This module only draws inputs; it holds none of the solver's arithmetic, and
+both the GPU path and the CPU checker are fed from it.  All draws use numpy's
+PCG64 with an explicit seed.  Arrays are float32 holding values that are exact
+in FP32 and FP64 (integers, or multiples of 2^-8), so energies are exact sums.
+
+Layout: ``w`` has the grid shape ``(H, W)`` or ``(D, H, W)``, W contiguous;
+``a`` is a list with one array per axis (0 = W, 1 = H, 2 = D) of the same
+shape, ``a[j][i]`` the weight of edge ``(i, i + stride_j)``; the last slice
+along axis ``j`` is zero.
+
+Workloads (the paper's maxflow-benchmark volumes are not available; these
+stand in for them):
+  * ``iid_grid``      -- integer unaries U{-20..20}, integer weights U{0..10}.
+  * ``ellipse_grid``  -- two-region piecewise-constant image (random ellipses
+                         or ellipsoids, intensities 0.3 / 0.7) plus Gaussian
+                         noise; w = cost of the foreground label (negative
+                         log-likelihood ratio), a = lam * exp(-dI^2 / (2 0.1^2)),
+                         both rounded to multiples of 2^-8.
+  * ``batch_sizes``   -- uneven (H, W) pairs for batched solves.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+DYADIC = 2.0 ** -8
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def _zero_last(a, axis_from_end):
+    """Zero the last slice along the axis (0 = W = last numpy axis)."""
+    idx = [slice(None)] * a.ndim
+    idx[a.ndim - 1 - axis_from_end] = -1
+    a[tuple(idx)] = 0
+    return a
+
+
+def iid_grid(shape, seed, w_max=20, a_max=10):
+    """Integer unaries U{-w_max..w_max} and weights U{0..a_max} on every axis."""
+    rng = _rng(seed)
+    shape = tuple(int(s) for s in shape)
+    w = rng.integers(-w_max, w_max + 1, size=shape).astype(np.float32)
+    a = []
+    for j in range(len(shape)):
+        aj = rng.integers(0, a_max + 1, size=shape).astype(np.float32)
+        a.append(_zero_last(aj, j))
+    return w, a
+
+
+def _quantise(x):
+    return (np.round(np.asarray(x, np.float64) / DYADIC) * DYADIC).astype(np.float32)
+
+
+def ellipse_image(shape, seed, sigma=0.15, k_range=(3, 8), axes_frac=(0.05, 0.25)):
+    """Noisy two-region image in [D][H][W] or [H][W]: 0.7 inside random ellipses."""
+    rng = _rng(seed)
+    shape = tuple(int(s) for s in shape)
+    nd = len(shape)
+    k = int(rng.integers(k_range[0], k_range[1] + 1))
+    grids = np.meshgrid(*[np.arange(s, dtype=np.float64) + 0.5 for s in shape], indexing="ij")
+    coords = np.stack([g.ravel() for g in grids], axis=1)  # (n, nd), numpy axis order
+    inside = np.zeros(coords.shape[0], dtype=bool)
+    ext = np.array(shape, dtype=np.float64)
+    for _ in range(k):
+        centre = rng.uniform(0, 1, size=nd) * ext
+        if nd == 2:
+            semi = rng.uniform(axes_frac[0], axes_frac[1], size=2) * min(shape)
+            ang = rng.uniform(0, np.pi)
+            c, s = np.cos(ang), np.sin(ang)
+            rot = np.array([[c, -s], [s, c]])
+        else:
+            semi = rng.uniform(axes_frac[0], axes_frac[1], size=3) * ext
+            q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+            rot = q * np.sign(np.diag(r))
+        d = (coords - centre) @ rot
+        inside |= np.sum((d / semi) ** 2, axis=1) <= 1.0
+    img = np.where(inside, 0.7, 0.3).reshape(shape)
+    img = img + rng.normal(0.0, sigma, size=shape)
+    return img
+
+
+def ellipse_grid(shape, seed, lam=2.0, sigma=0.15, beta_sigma=0.1):
+    """Segmentation-shaped cut problem from a noisy ellipse (ellipsoid) image."""
+    img = ellipse_image(shape, seed, sigma=sigma)
+    w = ((img - 0.7) ** 2 - (img - 0.3) ** 2) / (2.0 * sigma ** 2)
+    a = []
+    nd = img.ndim
+    for j in range(nd):
+        ax = nd - 1 - j  # numpy axis of grid axis j
+        nxt = np.roll(img, -1, axis=ax)
+        aj = lam * np.exp(-((nxt - img) ** 2) / (2.0 * beta_sigma ** 2))
+        a.append(_zero_last(_quantise(aj), j))
+    return _quantise(w), a
+
+
+def batch_sizes(count, seed, lo=128, hi=1024):
+    """`count` (H, W) pairs, each dimension uniform on [lo, hi]."""
+    rng = _rng(seed)
+    return [tuple(int(v) for v in rng.integers(lo, hi + 1, size=2)) for _ in range(count)]
+
+
+# Named workloads ----------------------------------------------------------
+
+def config_small(seed=1000):
+    """64x64 4-connected grid, integer data."""
+    return iid_grid((64, 64), seed)
+
+
+def config_image2d(seed=2000, shape=(1024, 1024)):
+    """1024x1024 segmentation-shaped grid, lambda = 2."""
+    return ellipse_grid(shape, seed, lam=2.0)
+
+
+def config_volume3d(seed=3000, shape=(128, 256, 256)):
+    """256x256x128 (W x H x D) 6-connected volume, lambda = 1.5."""
+    return ellipse_grid(shape, seed, lam=1.5)
+
+
+def config_batch(seed=4000, count=64):
+    """64 uneven integer grids: list of (w, a)."""
+    sizes = batch_sizes(count, seed)
+    return [iid_grid(hw, seed + 1 + g) for g, hw in enumerate(sizes)]
+
+
+def config_warm(seed, shape=(512, 512)):
+    """512x512 integer grid for the learned warm start."""
+    return iid_grid(shape, seed)
