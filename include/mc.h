@@ -1,0 +1,153 @@
+/*
+ * mc.h -- C ABI of libmc, a GPU (gfx950) solver for grid min-cut problems by
+ * decomposed total-variation denoising and Douglas-Rachford splitting, after
+ * Kumar, Barbero, Jegelka, Sra and Bach, "Convex Optimization for Parallel
+ * Energy Minimization" (arXiv:1503.01563).
+ *
+ * Problem.  A 2D 4-connected grid {H, W} or 3D 6-connected grid {D, H, W}
+ * (W contiguous, row-major) with unaries w and non-negative edge weights a.
+ * The cut energy of a labelling S (label 1 = in S) is
+ *     E(S) = sum_{i in S} w_i + sum_edges a_e [edge e crosses S]        (Sec. 2, eq. (4))
+ * i.e. the paper's f(x) - w^T x with the paper's w equal to -w here.  The
+ * solver minimises the TV problem min_x f(x) + 1/2 |x + w|^2 (Sec. 2.3,
+ * eq. (TV)), splits f into row / column / depth chain TVs (Sec. 3.1), runs
+ * averaged alternating reflections over exact chain proxes (Sec. 3.3, 4.3)
+ * and reads the cut off by thresholding x (Sec. 2.3), certified by the dual
+ * gap of Sec. 2.2.
+ *
+ * Edge weights.  One array per axis: axis 0 = W (stride 1), axis 1 = H
+ * (stride W), axis 2 = D (stride H*W).  a[j][i] is the weight of the edge
+ * (i, i + stride_j); entries on the last slice along axis j are ignored
+ * (with MC_VALIDATE they must be 0).  Weights must be >= 0 (Sec. 2: the
+ * pairwise terms are submodular cut weights).
+ *
+ * Memory.  Every array argument is a DEVICE pointer owned by the caller,
+ * contiguous, in the grid layout above, float32 unless stated; 256-byte
+ * alignment is recommended.  Host-side outputs (mc_stats, energies) are
+ * host pointers.  The library owns only the workspace inside mc_ctx.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * Work is enqueued on it; functions that fill host outputs synchronise it.
+ *
+ * Errors.  Every function returns an MC_* code; nothing throws across the
+ * ABI.  mc_last_error() gives a thread-local message for the last failure.
+ *
+ * Threading.  One context per host thread; a context is bound to the device
+ * it was created on.  Identical inputs give identical outputs (all
+ * reductions use fixed trees; no floating-point atomics).
+ */
+#ifndef MC_H
+#define MC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MC_OK 0
+#define MC_NOT_CONVERGED 1       /* max_iters reached; outputs are the last iterate */
+#define MC_ERR_INVALID_ARG (-1)  /* null pointer, bad dims, n > 2^31-1, bad axis, bad opts */
+#define MC_ERR_NEGATIVE_WEIGHT (-2) /* MC_VALIDATE only: some a < 0 (or non-zero on a last slice) */
+#define MC_ERR_NONFINITE (-3)    /* MC_VALIDATE only: NaN/Inf in w or a */
+#define MC_ERR_NOMEM (-4)        /* workspace allocation failed */
+#define MC_ERR_DEVICE (-5)       /* HIP runtime error; text in mc_last_error() */
+#define MC_ERR_NUMERIC (-6)      /* NaN/Inf appeared in the solver state */
+
+/* mc_opts.flags */
+#define MC_VALIDATE 1u           /* check inputs on the device before solving */
+
+/* mc_opts.variant */
+#define MC_VARIANT_AUTO 0        /* two-set form for 2D, product space for 3D */
+#define MC_VARIANT_TWO_SET 1     /* r = 2 special case (Sec. 3.3), 2D only */
+#define MC_VARIANT_PRODUCT 2     /* product-space form (Sec. 3.3, eq. (dualA)) */
+
+typedef struct mc_ctx mc_ctx;
+
+typedef struct {
+    int32_t ndim;     /* 2 or 3 */
+    int32_t reserved;
+    int64_t dims[3];  /* ndim 2: {H, W}; ndim 3: {D, H, W} */
+} mc_grid;
+
+typedef struct {
+    int32_t max_iters;    /* iteration cap (default 500) */
+    int32_t check_every;  /* certificate cadence in iterations (default 1) */
+    double gap_tol;       /* stop when cert = E(S) - LB(y) < gap_tol (default 1e-3) */
+    int32_t variant;      /* MC_VARIANT_* */
+    float tau0;           /* labels S_tau = {x > tau}, tau in (+tau0, 0, -tau0) (default 1e-3) */
+    uint32_t flags;       /* MC_VALIDATE */
+    int32_t reserved[4];
+} mc_opts;
+
+typedef struct {
+    int32_t status;       /* MC_OK or MC_NOT_CONVERGED */
+    int32_t iters;        /* iterations run */
+    double cert_gap;      /* E(S) - LB(y) at the last check (Sec. 2.2 gap at x = 1_S) */
+    double energy;        /* E(S) of the returned labels, FP64 */
+    double lower_bound;   /* LB(y) = sum_i min(y_i + w_i, 0), y rebuilt from clipped duals */
+    double tv_gap;        /* TV duality gap at the FP32 primal estimate (diagnostic) */
+    float tau_used;       /* threshold of the returned labels */
+    float ms;             /* device time of the solve (hipEvent), milliseconds */
+} mc_stats;
+
+/* Fill `o` with the defaults listed above. */
+void mc_opts_default(mc_opts *o);
+
+/* Create / destroy a context on `device` (HIP ordinal).  The context owns
+ * the solver workspace, which grows to the largest grid solved. */
+int mc_ctx_create(mc_ctx **out, int device);
+int mc_ctx_destroy(mc_ctx *ctx);
+
+/*
+ * mc_tv_solve -- minimum cut of one grid (Sec. 2-4).
+ *   w          [n] unaries.
+ *   a          host array of ndim device pointers, a[j] = [n] weights along axis j.
+ *   z0         nullable warm start of the splitting state (Sec. 4.4: reuse of
+ *              the dual vectors); n entries for the two-set form, ndim*n for
+ *              the product space (family j at offset j*n).
+ *   x_out      nullable [n]: primal TV estimate x = -w - sum_j D_j^T p_j at the last
+ *              check, p the edge duals of the chain proxes clipped to [-a, a].
+ *   labels_out [n] uint8, 1 = in S.
+ *   z_out      nullable: final state, same size as z0.
+ *   stats      host, required.
+ * Returns MC_OK when cert < gap_tol (the labels are then a minimum cut
+ * whenever all energies are multiples of a granularity g > gap_tol, e.g.
+ * integer or 2^-8-dyadic data), MC_NOT_CONVERGED at max_iters, or an error.
+ */
+int mc_tv_solve(mc_ctx *ctx, const mc_grid *grid, const float *w,
+                const float *const *a, const float *z0, float *x_out,
+                uint8_t *labels_out, float *z_out, mc_stats *stats,
+                const mc_opts *opts, void *stream);
+
+/*
+ * mc_tv_prox_chains -- exact weighted 1D-TV prox of every line along `axis`
+ * (Sec. 3.2): for each chain, x = argmin 1/2|x - v|^2 + sum_e a_e |x_{e+1} - x_e|.
+ *   v, a_axis  [n] input and weights along the axis.
+ *   x_out      [n] prox output.
+ *   p_out      nullable [n]: edge duals p_e (x = v - D^T p, |p_e| <= a_e, clipped),
+ *              stored at the edge's first voxel; 0 on the last slice.
+ */
+int mc_tv_prox_chains(mc_ctx *ctx, const mc_grid *grid, int axis,
+                      const float *v, const float *a_axis, float *x_out,
+                      float *p_out, void *stream);
+
+/*
+ * mc_cut_energy -- E(S) of eq. (4) in FP64 with a fixed reduction order;
+ * exact for integer and dyadic data.  labels [n] uint8 (non-zero = in S).
+ * Synchronises the stream; energy_out is a host pointer.
+ */
+int mc_cut_energy(mc_ctx *ctx, const mc_grid *grid, const float *w,
+                  const float *const *a, const uint8_t *labels,
+                  double *energy_out, void *stream);
+
+/* Text for a status code, and the calling thread's last error message. */
+const char *mc_status_string(int code);
+const char *mc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MC_H */

@@ -1,0 +1,315 @@
+// api.hip -- the C ABI declared in include/mc.h: contexts, workspace,
+// argument checks and the host loop of the splitting method.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "launch.hpp"
+#include "mc.h"
+
+using namespace mc;
+
+struct mc_ctx {
+    int device = 0;
+    size_t cap_n = 0;   // voxels the workspace was sized for
+    int cap_r = 0;      // families the workspace was sized for
+    float* z = nullptr;      // r*n splitting state
+    float* t = nullptr;      // n   (two-set: column input)
+    float* y = nullptr;      // max(1, r-1)*n  (two-set: y1; product: y_j of non-final families)
+    float* p = nullptr;      // r*n edge duals (check iterations)
+    float* xt = nullptr;     // n   primal estimate -w - sum_j D_j^T p_j (check iterations)
+    SegRec* rec = nullptr;   // r*n segment records
+    double* partials = nullptr;  // kReduceBlocks * kCertValues
+    double* dout = nullptr;      // 8 doubles
+    double* hout = nullptr;      // 8 doubles, pinned host
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg)
+{
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* where)
+{
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(MC_ERR_DEVICE, m);
+}
+
+#define MC_HIP(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+int make_geo(const mc_grid* grid, Geo* g)
+{
+    if (!grid) return fail(MC_ERR_INVALID_ARG, "grid is null");
+    int64_t D, H, W;
+    if (grid->ndim == 2) {
+        D = 1; H = grid->dims[0]; W = grid->dims[1];
+    } else if (grid->ndim == 3) {
+        D = grid->dims[0]; H = grid->dims[1]; W = grid->dims[2];
+    } else {
+        return fail(MC_ERR_INVALID_ARG, "ndim must be 2 or 3");
+    }
+    if (D <= 0 || H <= 0 || W <= 0) return fail(MC_ERR_INVALID_ARG, "dims must be positive");
+    const int64_t n = D * H * W;
+    if (n > INT32_MAX || D > INT32_MAX || H > INT32_MAX || W > INT32_MAX)
+        return fail(MC_ERR_INVALID_ARG, "grid has more than 2^31-1 nodes");
+    if (W >= (1 << 30) || H >= (1 << 30) || D >= (1 << 30))
+        return fail(MC_ERR_INVALID_ARG, "chain length must be below 2^30");
+    g->D = (int)D; g->H = (int)H; g->W = (int)W;
+    g->n = (int)n;
+    g->ndim = grid->ndim;
+    return MC_OK;
+}
+
+void free_ws(mc_ctx* c)
+{
+    hipFree(c->z); hipFree(c->t); hipFree(c->y); hipFree(c->p); hipFree(c->xt);
+    hipFree(c->rec);
+    c->z = c->t = c->y = c->p = c->xt = nullptr;
+    c->rec = nullptr;
+    c->cap_n = 0;
+    c->cap_r = 0;
+}
+
+int ensure_ws(mc_ctx* c, size_t n, int r)
+{
+    if (c->cap_n >= n && c->cap_r >= r && c->z) return MC_OK;
+    size_t nn = n > c->cap_n ? n : c->cap_n;
+    int rr = r > c->cap_r ? r : c->cap_r;
+    free_ws(c);
+    const size_t fb = sizeof(float);
+    const int ry = rr > 1 ? rr - 1 : 1;
+    if (hipMalloc(&c->z, fb * nn * rr) != hipSuccess || hipMalloc(&c->t, fb * nn) != hipSuccess ||
+        hipMalloc(&c->y, fb * nn * ry) != hipSuccess || hipMalloc(&c->p, fb * nn * rr) != hipSuccess ||
+        hipMalloc(&c->xt, fb * nn) != hipSuccess ||
+        hipMalloc(&c->rec, sizeof(SegRec) * nn * rr) != hipSuccess) {
+        free_ws(c);
+        (void)hipGetLastError();
+        return fail(MC_ERR_NOMEM, "workspace allocation failed");
+    }
+    c->cap_n = nn;
+    c->cap_r = rr;
+    return MC_OK;
+}
+
+int check_ctx(mc_ctx* c)
+{
+    if (!c) return fail(MC_ERR_INVALID_ARG, "ctx is null");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return MC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mc_opts_default(mc_opts* o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->max_iters = 500;
+    o->check_every = 1;
+    o->gap_tol = 1e-3;
+    o->variant = MC_VARIANT_AUTO;
+    o->tau0 = 1e-3f;
+    o->flags = 0;
+}
+
+const char* mc_status_string(int code)
+{
+    switch (code) {
+    case MC_OK: return "ok";
+    case MC_NOT_CONVERGED: return "not converged (max_iters reached)";
+    case MC_ERR_INVALID_ARG: return "invalid argument";
+    case MC_ERR_NEGATIVE_WEIGHT: return "negative edge weight (or non-zero weight on a last slice)";
+    case MC_ERR_NONFINITE: return "non-finite input";
+    case MC_ERR_NOMEM: return "out of device memory";
+    case MC_ERR_DEVICE: return "HIP runtime error";
+    case MC_ERR_NUMERIC: return "non-finite solver state";
+    default: return "unknown status";
+    }
+}
+
+const char* mc_last_error(void) { return g_last_error.c_str(); }
+
+int mc_ctx_create(mc_ctx** out, int device)
+{
+    if (!out) return fail(MC_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(MC_ERR_INVALID_ARG, "no such device");
+    MC_HIP(hipSetDevice(device));
+    mc_ctx* c = new mc_ctx();
+    c->device = device;
+    if (hipMalloc(&c->partials, sizeof(double) * kReduceBlocks * kCertValues) != hipSuccess ||
+        hipMalloc(&c->dout, sizeof(double) * 8) != hipSuccess ||
+        hipHostMalloc(&c->hout, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        (void)hipGetLastError();
+        mc_ctx_destroy(c);
+        return fail(MC_ERR_NOMEM, "context allocation failed");
+    }
+    *out = c;
+    return MC_OK;
+}
+
+int mc_ctx_destroy(mc_ctx* c)
+{
+    if (!c) return MC_OK;
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    free_ws(c);
+    hipFree(c->partials);
+    hipFree(c->dout);
+    if (c->hout) hipHostFree(c->hout);
+    if (c->ev0) hipEventDestroy(c->ev0);
+    if (c->ev1) hipEventDestroy(c->ev1);
+    delete c;
+    return MC_OK;
+}
+
+int mc_tv_prox_chains(mc_ctx* c, const mc_grid* grid, int axis, const float* v,
+                      const float* a_axis, float* x_out, float* p_out, void* stream)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    Geo g;
+    if ((rc = make_geo(grid, &g))) return rc;
+    if (axis < 0 || axis >= g.ndim) return fail(MC_ERR_INVALID_ARG, "axis out of range");
+    if (!v || !a_axis || !x_out) return fail(MC_ERR_INVALID_ARG, "null array");
+    if ((rc = ensure_ws(c, (size_t)g.n, 1))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    MC_HIP(launch_prox(g, axis, v, a_axis, x_out, p_out, c->rec, s));
+    return MC_OK;
+}
+
+int mc_cut_energy(mc_ctx* c, const mc_grid* grid, const float* w, const float* const* a,
+                  const uint8_t* labels, double* energy_out, void* stream)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    Geo g;
+    if ((rc = make_geo(grid, &g))) return rc;
+    if (!w || !a || !labels || !energy_out) return fail(MC_ERR_INVALID_ARG, "null argument");
+    for (int j = 0; j < g.ndim; ++j)
+        if (!a[j]) return fail(MC_ERR_INVALID_ARG, "null weight array");
+    hipStream_t s = (hipStream_t)stream;
+    MC_HIP(launch_energy(g, w, a, labels, c->partials, c->dout, s));
+    MC_HIP(hipMemcpyAsync(c->hout, c->dout, sizeof(double), hipMemcpyDeviceToHost, s));
+    MC_HIP(hipStreamSynchronize(s));
+    *energy_out = c->hout[0];
+    return MC_OK;
+}
+
+int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* const* a,
+                const float* z0, float* x_out, uint8_t* labels_out, float* z_out,
+                mc_stats* stats, const mc_opts* opts_in, void* stream)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    Geo g;
+    if ((rc = make_geo(grid, &g))) return rc;
+    if (!w || !a || !labels_out || !stats) return fail(MC_ERR_INVALID_ARG, "null argument");
+    for (int j = 0; j < g.ndim; ++j)
+        if (!a[j]) return fail(MC_ERR_INVALID_ARG, "null weight array");
+    mc_opts o;
+    if (opts_in) o = *opts_in; else mc_opts_default(&o);
+    if (o.max_iters < 1 || o.check_every < 1) return fail(MC_ERR_INVALID_ARG, "max_iters and check_every must be >= 1");
+    if (!(o.tau0 >= 0.f)) return fail(MC_ERR_INVALID_ARG, "tau0 must be >= 0");
+    bool two_set;
+    if (o.variant == MC_VARIANT_AUTO) two_set = g.ndim == 2;
+    else if (o.variant == MC_VARIANT_TWO_SET) two_set = true;
+    else if (o.variant == MC_VARIANT_PRODUCT) two_set = false;
+    else return fail(MC_ERR_INVALID_ARG, "unknown variant");
+    if (two_set && g.ndim != 2) return fail(MC_ERR_INVALID_ARG, "two-set form needs a 2D grid");
+    const int r = g.ndim;
+    const size_t n = (size_t)g.n;
+    const size_t nz = two_set ? n : (size_t)r * n;
+    if ((rc = ensure_ws(c, n, r))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+
+    if (o.flags & MC_VALIDATE) {
+        MC_HIP(launch_validate(g, w, a, c->partials, c->dout, s));
+        MC_HIP(hipMemcpyAsync(c->hout, c->dout, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        if (c->hout[1] > 0) return fail(MC_ERR_NONFINITE, "non-finite value in w or a");
+        if (c->hout[0] > 0) return fail(MC_ERR_NEGATIVE_WEIGHT, "negative weight or non-zero weight on a last slice");
+    }
+
+    if (z0) MC_HIP(hipMemcpyAsync(c->z, z0, sizeof(float) * nz, hipMemcpyDeviceToDevice, s));
+    else MC_HIP(hipMemsetAsync(c->z, 0, sizeof(float) * nz, s));
+    MC_HIP(hipEventRecord(c->ev0, s));
+
+    const float* pj[3] = {c->p, c->p + n, c->p + 2 * n};
+    const float taus[3] = {o.tau0, 0.f, -o.tau0};
+    int it = 0;
+    bool converged = false;
+    double cert = INFINITY, energy = INFINITY, lb = -INFINITY, tvgap = NAN;
+    float tau_used = 0.f;
+    while (it < o.max_iters) {
+        ++it;
+        const bool check = (it % o.check_every == 0) || it == o.max_iters;
+        if (two_set) {
+            MC_HIP(launch_dr2_rows(g, c->z, a[0], w, c->t, c->y, check ? c->p : nullptr, c->rec, s));
+            MC_HIP(launch_dr2_cols(g, c->t, a[1], c->y, c->z, check ? c->p + n : nullptr, c->rec, s));
+        } else {
+            MC_HIP(launch_drp_sweeps(g, r - 1, c->z, a, c->y, check ? c->p : nullptr, c->rec, s));
+            MC_HIP(launch_drp_final(g, r, c->z, c->y, a[r - 1], w,
+                                    check ? c->p + (size_t)(r - 1) * n : nullptr,
+                                    c->rec + (size_t)(r - 1) * n, s));
+        }
+        if (!check) continue;
+        MC_HIP(launch_cert(g, w, a, pj, o.tau0, c->xt, c->partials, c->dout, s));
+        MC_HIP(hipMemcpyAsync(c->hout, c->dout, kCertValues * sizeof(double), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        energy = INFINITY;
+        for (int k = 0; k < 3; ++k) {
+            if (c->hout[k] < energy) {
+                energy = c->hout[k];
+                tau_used = taus[k];
+            }
+        }
+        tvgap = c->hout[3];
+        lb = c->hout[4];
+        cert = energy - lb;
+        if (!isfinite(cert)) return fail(MC_ERR_NUMERIC, "non-finite certificate (NaN/Inf in the state)");
+        if (cert < o.gap_tol) {
+            converged = true;
+            break;
+        }
+    }
+    MC_HIP(hipEventRecord(c->ev1, s));
+    MC_HIP(launch_labels(g, c->xt, tau_used, labels_out, s));
+    if (x_out) MC_HIP(hipMemcpyAsync(x_out, c->xt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    if (z_out) MC_HIP(hipMemcpyAsync(z_out, c->z, sizeof(float) * nz, hipMemcpyDeviceToDevice, s));
+    MC_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    MC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    stats->status = converged ? MC_OK : MC_NOT_CONVERGED;
+    stats->iters = it;
+    stats->cert_gap = cert;
+    stats->energy = energy;
+    stats->lower_bound = lb;
+    stats->tv_gap = tvgap;
+    stats->tau_used = tau_used;
+    stats->ms = ms;
+    return stats->status;
+}
+
+}  // extern "C"

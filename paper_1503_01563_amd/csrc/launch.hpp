@@ -1,0 +1,75 @@
+// launch.hpp -- host-side launchers for the libmc kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "chain.hpp"
+
+namespace mc {
+
+// Grid geometry: [D][H][W], W contiguous; 2D grids have D = 1.
+struct Geo {
+    int D, H, W;
+    int n;
+    int ndim;
+};
+
+__host__ __device__ inline int geo_extent(const Geo& g, int axis)
+{
+    return axis == 0 ? g.W : (axis == 1 ? g.H : g.D);
+}
+__host__ __device__ inline int geo_stride(const Geo& g, int axis)
+{
+    return axis == 0 ? 1 : (axis == 1 ? g.W : g.W * g.H);
+}
+__host__ __device__ inline int geo_nchains(const Geo& g, int axis) { return g.n / geo_extent(g, axis); }
+
+constexpr int kReduceBlocks = 512;   // blocks of the reduction kernels (fixed: deterministic)
+constexpr int kReduceThreads = 256;
+constexpr int kCertValues = 5;       // E(+tau0), E(0), E(-tau0), TV gap, LB
+
+// Standalone prox of every chain along `axis` (x = prox(v), p = clipped duals).
+hipError_t launch_prox(const Geo& g, int axis, const float* v, const float* a, float* x,
+                       float* p, SegRec* rec, hipStream_t s);
+
+// Two-set splitting, rows: q1 = prox_rows(z); y1 = z - q1; t = -w - y1 + q1.
+hipError_t launch_dr2_rows(const Geo& g, const float* z, const float* a_x, const float* w,
+                           float* t, float* y1, float* p1, SegRec* rec, hipStream_t s);
+
+// Two-set splitting, columns: q2 = prox_cols(t); z <- y1 + q2; p2 on checks.
+hipError_t launch_dr2_cols(const Geo& g, const float* t, const float* a_y, const float* y1,
+                           float* z, float* p2, SegRec* rec, hipStream_t s);
+
+// Product space, non-final families: y_j = z_j - prox_j(z_j) for each axis in
+// [0, nfam) (one launch); p_j written when p != nullptr.
+hipError_t launch_drp_sweeps(const Geo& g, int nfam, const float* z, const float* const* a,
+                             float* y, float* p, SegRec* rec, hipStream_t s);
+
+// Product space, final family (axis r-1) fused with the average over L:
+// z_j <- y_j - (2Y - Z - u)/r; p_{r-1} on checks.
+hipError_t launch_drp_final(const Geo& g, int r, float* z, const float* y, const float* a_last,
+                            const float* w, float* p_last, SegRec* rec, hipStream_t s);
+
+// Certificate from the edge duals p: primal xc = -w - sum_j D_j^T p_j (FP32
+// out), then out[5] = {E(+tau0), E(0), E(-tau0), TV gap, LB} in FP64.
+// partials needs 5 * kReduceBlocks doubles.
+hipError_t launch_cert(const Geo& g, const float* w, const float* const* a,
+                       const float* const* p, float tau0, float* xc, double* partials,
+                       double* out, hipStream_t s);
+
+hipError_t launch_labels(const Geo& g, const float* xc, float tau, uint8_t* labels, hipStream_t s);
+
+hipError_t launch_energy(const Geo& g, const float* w, const float* const* a,
+                         const uint8_t* labels, double* partials, double* out, hipStream_t s);
+
+// Input checks: out[0] = #negative weights or non-zero weights on a last slice,
+// out[1] = #non-finite values in w and a.
+hipError_t launch_validate(const Geo& g, const float* w, const float* const* a,
+                           double* partials, double* out, hipStream_t s);
+
+// Non-finite entries in an array (out[0]).
+hipError_t launch_count_nonfinite(const float* x, int n, double* partials, double* out,
+                                  hipStream_t s);
+
+}  // namespace mc

@@ -1,0 +1,243 @@
+"""Python binding of libmc (include/mc.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module checks tensor
+shapes, dtypes and devices, passes device pointers and the current HIP stream,
+and converts the returned status into exceptions.  There is no fallback: if
+libmc.so is missing or cannot be loaded, every call raises.
+
+Arrays are torch tensors on a ROCm device: ``w`` of the grid shape (H, W) or
+(D, H, W), float32, contiguous; ``a`` a sequence with one tensor of the same
+shape per axis (axis 0 = W, 1 = H, 2 = D).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmc.so")
+
+MC_OK = 0
+MC_NOT_CONVERGED = 1
+MC_VALIDATE = 1
+VARIANT_AUTO, VARIANT_TWO_SET, VARIANT_PRODUCT = 0, 1, 2
+
+
+class McError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libmc error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dims", ctypes.c_int64 * 3)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("max_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("gap_tol", ctypes.c_double), ("variant", ctypes.c_int32),
+                ("tau0", ctypes.c_float), ("flags", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("cert_gap", ctypes.c_double), ("energy", ctypes.c_double),
+                ("lower_bound", ctypes.c_double), ("tv_gap", ctypes.c_double),
+                ("tau_used", ctypes.c_float), ("ms", ctypes.c_float)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library():
+    """Load libmc.so (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise McError(-100, "libmc.so not found at %s; run paper_1503_01563_amd.build" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        lib.mc_opts_default.argtypes = [ctypes.POINTER(Opts)]
+        lib.mc_opts_default.restype = None
+        lib.mc_ctx_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+        lib.mc_ctx_create.restype = ctypes.c_int
+        lib.mc_ctx_destroy.argtypes = [P]
+        lib.mc_ctx_destroy.restype = ctypes.c_int
+        lib.mc_tv_solve.argtypes = [P, ctypes.POINTER(Grid), P, P, P, P, P, P,
+                                    ctypes.POINTER(Stats), ctypes.POINTER(Opts), P]
+        lib.mc_tv_solve.restype = ctypes.c_int
+        lib.mc_tv_prox_chains.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int, P, P, P, P, P]
+        lib.mc_tv_prox_chains.restype = ctypes.c_int
+        lib.mc_cut_energy.argtypes = [P, ctypes.POINTER(Grid), P, P, P, ctypes.POINTER(ctypes.c_double), P]
+        lib.mc_cut_energy.restype = ctypes.c_int
+        lib.mc_status_string.argtypes = [ctypes.c_int]
+        lib.mc_status_string.restype = ctypes.c_char_p
+        lib.mc_last_error.argtypes = []
+        lib.mc_last_error.restype = ctypes.c_char_p
+        _lib = lib
+        return lib
+
+
+def _check(rc, allow_not_converged=False):
+    if rc == MC_OK or (allow_not_converged and rc == MC_NOT_CONVERGED):
+        return rc
+    lib = load_library()
+    raise McError(rc, "%s: %s" % (lib.mc_status_string(rc).decode(), lib.mc_last_error().decode()))
+
+
+_ctx = {}
+
+
+def context(device: int):
+    """Per-(thread, device) libmc context."""
+    key = (threading.get_ident(), device)
+    if key not in _ctx:
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.mc_ctx_create(ctypes.byref(h), device))
+        _ctx[key] = h
+    return _ctx[key]
+
+
+def _grid(shape):
+    g = Grid()
+    g.ndim = len(shape)
+    if g.ndim not in (2, 3):
+        raise ValueError("grid must be 2D or 3D")
+    for k, s in enumerate(shape):
+        g.dims[k] = int(s)
+    return g
+
+
+def _dev_f32(t, shape, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError("%s must be a torch tensor on a ROCm device" % name)
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32" % name)
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError("%s must be contiguous with shape %s" % (name, tuple(shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _aptrs(a, shape, nd):
+    if len(a) != nd:
+        raise ValueError("need one weight array per axis")
+    return (ctypes.c_void_p * 3)(*([_dev_f32(a[j], shape, "a[%d]" % j).value for j in range(nd)]
+                                   + [None] * (3 - nd)))
+
+
+@dataclass
+class SolveResult:
+    labels: torch.Tensor
+    x: Optional[torch.Tensor]
+    z: Optional[torch.Tensor]
+    status: int
+    iters: int
+    cert_gap: float
+    energy: float
+    lower_bound: float
+    tau_used: float
+    ms: float
+
+    @property
+    def converged(self):
+        return self.status == MC_OK
+
+
+def make_opts(max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
+              validate=False):
+    o = Opts()
+    load_library().mc_opts_default(ctypes.byref(o))
+    o.max_iters = int(max_iters)
+    o.check_every = int(check_every)
+    o.gap_tol = float(gap_tol)
+    o.variant = int(variant)
+    o.tau0 = float(tau0)
+    o.flags = MC_VALIDATE if validate else 0
+    return o
+
+
+def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tensor] = None,
+             max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
+             validate=False, return_x=True, return_z=False, labels_out=None) -> SolveResult:
+    """Minimum cut of one grid by mc_tv_solve."""
+    lib = load_library()
+    shape = tuple(w.shape)
+    nd = len(shape)
+    dev = w.device.index if w.device.index is not None else torch.cuda.current_device()
+    wp = _dev_f32(w, shape, "w")
+    ap = _aptrs(a, shape, nd)
+    two_set = (variant == VARIANT_TWO_SET) or (variant == VARIANT_AUTO and nd == 2)
+    nz = w.numel() if two_set else nd * w.numel()
+    z0p = None
+    if z0 is not None:
+        if z0.device != w.device or z0.dtype != torch.float32 or not z0.is_contiguous() or z0.numel() != nz:
+            raise ValueError("z0 must be a contiguous float32 device tensor with %d entries" % nz)
+        z0p = ctypes.c_void_p(z0.data_ptr())
+    labels = labels_out if labels_out is not None else torch.empty(shape, dtype=torch.uint8, device=w.device)
+    if labels.dtype != torch.uint8 or tuple(labels.shape) != shape or not labels.is_contiguous():
+        raise ValueError("labels_out must be contiguous uint8 of the grid shape")
+    x = torch.empty(shape, dtype=torch.float32, device=w.device) if return_x else None
+    z = torch.empty(nz, dtype=torch.float32, device=w.device) if return_z else None
+    st = Stats()
+    o = make_opts(max_iters, check_every, gap_tol, variant, tau0, validate)
+    rc = lib.mc_tv_solve(context(dev), ctypes.byref(_grid(shape)), wp,
+                         ctypes.cast(ap, ctypes.c_void_p), z0p,
+                         ctypes.c_void_p(x.data_ptr()) if x is not None else None,
+                         ctypes.c_void_p(labels.data_ptr()),
+                         ctypes.c_void_p(z.data_ptr()) if z is not None else None,
+                         ctypes.byref(st), ctypes.byref(o), _stream(dev))
+    _check(rc, allow_not_converged=True)
+    return SolveResult(labels, x, z, st.status, st.iters, st.cert_gap, st.energy,
+                       st.lower_bound, st.tau_used, st.ms)
+
+
+def tv_prox_chains(v: torch.Tensor, a_axis: torch.Tensor, axis: int, return_p=False,
+                   x_out=None, p_out=None):
+    """Exact weighted 1D-TV prox of every line of `v` along `axis` (mc_tv_prox_chains)."""
+    lib = load_library()
+    shape = tuple(v.shape)
+    dev = v.device.index if v.device.index is not None else torch.cuda.current_device()
+    vp = _dev_f32(v, shape, "v")
+    apn = _dev_f32(a_axis, shape, "a_axis")
+    x = x_out if x_out is not None else torch.empty_like(v)
+    p = (p_out if p_out is not None else torch.empty_like(v)) if return_p else None
+    _dev_f32(x, shape, "x_out")
+    rc = lib.mc_tv_prox_chains(context(dev), ctypes.byref(_grid(shape)), int(axis), vp, apn,
+                               ctypes.c_void_p(x.data_ptr()),
+                               ctypes.c_void_p(p.data_ptr()) if p is not None else None,
+                               _stream(dev))
+    _check(rc)
+    return (x, p) if return_p else x
+
+
+def cut_energy(w: torch.Tensor, a: Sequence[torch.Tensor], labels: torch.Tensor) -> float:
+    """E(S) in FP64 on the device (mc_cut_energy)."""
+    lib = load_library()
+    shape = tuple(w.shape)
+    nd = len(shape)
+    dev = w.device.index if w.device.index is not None else torch.cuda.current_device()
+    wp = _dev_f32(w, shape, "w")
+    ap = _aptrs(a, shape, nd)
+    if labels.dtype != torch.uint8 or tuple(labels.shape) != shape or not labels.is_contiguous():
+        raise ValueError("labels must be contiguous uint8 of the grid shape")
+    e = ctypes.c_double(0)
+    rc = lib.mc_cut_energy(context(dev), ctypes.byref(_grid(shape)), wp,
+                           ctypes.cast(ap, ctypes.c_void_p), ctypes.c_void_p(labels.data_ptr()),
+                           ctypes.byref(e), _stream(dev))
+    _check(rc)
+    return e.value

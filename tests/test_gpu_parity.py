@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerances: FP32 chain proxes and TV iterates within 1e-4 relative L-inf of
+the FP64 oracle on identical FP32 inputs; cut energies bit-exact (integer and
+2^-8-dyadic data make every energy an exact FP64 sum, and a certificate below
+1e-3 is below the data's energy granularity).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_01563_amd import gen
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_01563_amd import mc
+    mc.load_library()
+    return torch.device("cuda:0")
+
+
+def to_dev(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+
+
+def rel_linf(x, ref):
+    return float(np.abs(np.asarray(x, np.float64) - ref).max() / max(1.0, np.abs(ref).max()))
+
+
+def chain_inputs(kind, shape, rng):
+    if kind == "random":
+        v = rng.normal(size=shape) * 5
+        a = rng.uniform(0, 2, size=shape)
+    elif kind == "integer":
+        v = rng.integers(-20, 21, size=shape).astype(float)
+        a = rng.integers(0, 11, size=shape).astype(float)
+    elif kind == "piecewise":
+        v = np.repeat(rng.normal(size=shape[:-1] + ((shape[-1] + 7) // 8,)) * 10, 8, axis=-1)[..., : shape[-1]]
+        v = v + rng.normal(size=shape) * 0.1
+        a = np.full(shape, 0.5)
+    elif kind == "staircase":
+        v = np.cumsum(rng.uniform(0, 3, size=shape), axis=-1)
+        a = np.full(shape, 2.0)
+    elif kind == "zero_runs":
+        v = rng.normal(size=shape)
+        a = np.where(rng.uniform(size=shape) < 0.4, 0.0, rng.uniform(0, 1, size=shape))
+    elif kind == "huge_a":
+        v = rng.normal(size=shape)
+        a = np.full(shape, 1e6)
+    elif kind == "offset":
+        v = rng.normal(size=shape) * 3 + 1e4
+        a = rng.uniform(0, 10, size=shape)
+    else:
+        raise ValueError(kind)
+    return v.astype(np.float32), a.astype(np.float32)
+
+
+KINDS = ["random", "integer", "piecewise", "staircase", "zero_runs", "huge_a", "offset"]
+
+
+@pytest.mark.parametrize("length", [1, 2, 3, 7, 8, 64, 127, 1024])
+@pytest.mark.parametrize("kind", KINDS)
+def test_prox_rows_parity(dev, length, kind):
+    from paper_1503_01563_amd import mc
+    rng = np.random.default_rng(length * 31 + KINDS.index(kind))
+    shape = (67, length)  # 67 chains: one full wave plus a ragged tail
+    v, a = chain_inputs(kind, shape, rng)
+    a[:, -1] = 0
+    x, p = mc.tv_prox_chains(to_dev(v, dev), to_dev(a, dev), 0, return_p=True)
+    xr, pr = oracle.prox_family(shape, 0, v.astype(np.float64), a.astype(np.float64))
+    assert rel_linf(x.cpu().numpy(), xr) <= REL_TOL
+    pg = p.cpu().numpy()
+    assert np.all(np.abs(pg) <= a)
+    assert np.all(pg[:, -1] == 0)
+    scale = max(1.0, np.abs(pr).max())
+    assert float(np.abs(pg - pr).max()) / scale <= REL_TOL
+
+
+@pytest.mark.parametrize("shape,axis", [((5, 33, 70), 0), ((5, 33, 70), 1), ((5, 33, 70), 2),
+                                        ((129, 3), 1), ((3, 129), 0), ((1, 1), 0), ((1, 1), 1),
+                                        ((1, 200), 1), ((200, 1), 0), ((40, 1, 9), 2)])
+def test_prox_axes_parity(dev, shape, axis):
+    from paper_1503_01563_amd import mc
+    rng = np.random.default_rng(sum(shape) + axis)
+    v = (rng.normal(size=shape) * 4).astype(np.float32)
+    a = rng.uniform(0, 2, size=shape).astype(np.float32)
+    x, p = mc.tv_prox_chains(to_dev(v, dev), to_dev(a, dev), axis, return_p=True)
+    xr, pr = oracle.prox_family(shape, axis, v.astype(np.float64), a.astype(np.float64))
+    assert rel_linf(x.cpu().numpy(), xr) <= REL_TOL
+
+
+@pytest.mark.parametrize("shape", [(64, 64), (37, 53), (1, 300), (300, 1), (9, 11, 13), (1, 1)])
+def test_cut_energy_bit_exact(dev, shape):
+    from paper_1503_01563_amd import mc
+    for seed in range(3):
+        w, a = gen.iid_grid(shape, 500 + seed)
+        if seed == 2:
+            w, a = gen.ellipse_grid(shape if len(shape) == 3 else shape, 900 + seed) \
+                if min(shape) > 1 else (w, a)
+        lab = (np.random.default_rng(seed).uniform(size=shape) < 0.5).astype(np.uint8)
+        import torch
+        e = mc.cut_energy(to_dev(w, dev), [to_dev(x, dev) for x in a], torch.from_numpy(lab).to(dev))
+        assert e == oracle.cut_energy(w, a, lab)
+
+
+@pytest.mark.parametrize("seed", list(range(1000, 1008)))
+def test_solve_small_grid_exact(dev, seed):
+    from paper_1503_01563_amd import mc
+    w, a = gen.config_small(seed)
+    e_star, mn, mx = oracle.mincut(w, a, "ek" if seed < 1002 else "dinic")
+    res = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=500, gap_tol=1e-3)
+    assert res.converged and res.cert_gap < 1e-3
+    assert res.energy == e_star
+    lab = res.labels.cpu().numpy()
+    assert oracle.cut_energy(w, a, lab) == e_star
+    ro = oracle.dr_solve(w, a, max_iters=500, gap_tol=1e-3)
+    print("seed %d: gpu iters %d, oracle iters %d" % (seed, res.iters, ro["iters"]))
+
+
+@pytest.mark.parametrize("shape,variant", [((37, 53), 1), ((37, 53), 2), ((6, 17, 23), 2),
+                                           ((1, 41), 1), ((41, 1), 1), ((5, 1, 7), 2)])
+@pytest.mark.parametrize("iters", [1, 3, 20])
+def test_dr_iterates_match_oracle(dev, shape, variant, iters):
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid(shape, 77 + iters)
+    res = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=iters, gap_tol=0.0,
+                      variant=variant, return_z=True)
+    assert res.iters == iters
+    ro = oracle.dr_solve(w, a, variant=0 if variant == 1 else 1, max_iters=iters, gap_tol=0,
+                         return_z=True)
+    assert rel_linf(res.x.cpu().numpy(), ro["x"]) <= REL_TOL
+    assert rel_linf(res.z.cpu().numpy(), ro["z"]) <= REL_TOL
+
+
+@pytest.mark.parametrize("shape,variant", [((24, 31), 1), ((24, 31), 2), ((6, 9, 11), 2)])
+def test_tv_solution_matches_oracle(dev, shape, variant):
+    from paper_1503_01563_amd import mc
+    # Reference: FP64 run stopped at TV gap 2e-8; by 1-strong convexity of
+    # the TV objective its distance to x* is at most sqrt(2 * 2e-8) = 2e-4,
+    # far below 1e-4 * |x*|_inf for these data (|x*| ~ 20).
+    w, a = gen.iid_grid(shape, 5)
+    ro = oracle.dr_solve(w, a, variant=0 if variant == 1 else 1, max_iters=6000, gap_tol=0,
+                         tv_tol=2e-8)
+    assert ro["tv_gap"] < 2e-8
+    res = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=ro["iters"],
+                      gap_tol=0.0, variant=variant)
+    assert rel_linf(res.x.cpu().numpy(), ro["x"]) <= REL_TOL
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 5), (2, 2, 4), (4, 4), (1, 16), (16, 1)])
+def test_solve_tiny_against_bruteforce(dev, shape):
+    from paper_1503_01563_amd import mc
+    for seed in range(4):
+        w, a = gen.iid_grid(shape, 40 + seed)
+        if seed % 2:
+            w = (np.round(w / 3.0 * 256) / 256).astype(np.float32)
+        if np.prod(shape) <= 20:
+            e_star, _, _, _ = oracle.bruteforce(w, a)
+        else:
+            e_star, _, _ = oracle.mincut(w, a, "ek")
+        res = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=2000)
+        assert res.converged and res.energy == e_star
+
+
+def test_degenerate_inputs(dev):
+    import torch
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid((20, 30), 3)
+    z = [np.zeros_like(x) for x in a]
+    res = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in z], max_iters=10)
+    assert res.converged and res.energy == float(np.minimum(w, 0).sum())
+    np.testing.assert_allclose(res.x.cpu().numpy(), -w, atol=1e-5)
+    res = mc.tv_solve(to_dev(np.zeros_like(w), dev), [to_dev(x, dev) for x in a], max_iters=10)
+    assert res.converged and res.energy == 0.0
+    c = np.full_like(w, -3.0)
+    res = mc.tv_solve(to_dev(c, dev), [to_dev(x, dev) for x in a], max_iters=50)
+    assert res.converged and res.energy == float(c.sum())
+    assert int(res.labels.sum()) == c.size
+    w1 = np.array([[5.0]], np.float32)
+    res = mc.tv_solve(to_dev(w1, dev), [to_dev(np.zeros_like(w1), dev)] * 2, max_iters=5)
+    assert res.converged and res.energy == 0.0
+
+
+def test_validation_errors(dev):
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid((8, 9), 1)
+    bad = [x.copy() for x in a]
+    bad[0][2, 3] = -1.0
+    with pytest.raises(mc.McError) as e:
+        mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in bad], validate=True)
+    assert e.value.code == -2
+    wn = w.copy()
+    wn[1, 1] = np.nan
+    with pytest.raises(mc.McError) as e:
+        mc.tv_solve(to_dev(wn, dev), [to_dev(x, dev) for x in a], validate=True)
+    assert e.value.code == -3
+    res = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=1, gap_tol=0.0)
+    assert res.status == 1 and res.iters == 1
+    with pytest.raises(mc.McError):
+        mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], variant=1, max_iters=0)
+
+
+def test_image2d_full_size_exact(dev):
+    """Segmentation-shaped 1024x1024 grid: exact energy against max-flow."""
+    from paper_1503_01563_amd import mc
+    w, a = gen.config_image2d(2000)
+    e_star, mn, mx = oracle.mincut(w, a, "dinic")
+    res = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=2000, gap_tol=1e-3)
+    print("1024^2: iters %d cert %.3g ms %.2f" % (res.iters, res.cert_gap, res.ms))
+    assert res.converged and res.energy == e_star
+    lab = res.labels.cpu().numpy()
+    assert oracle.cut_energy(w, a, lab) == e_star
+    assert np.all(lab >= mn) and np.all(lab <= mx)
+
+
+def test_volume3d_full_size_exact(dev):
+    """256x256x128 6-connected volume: exact energy against max-flow."""
+    from paper_1503_01563_amd import mc
+    w, a = gen.config_volume3d(3000)
+    e_star, mn, mx = oracle.mincut(w, a, "dinic")
+    res = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=3000, gap_tol=1e-3,
+                      check_every=5)
+    print("3D: iters %d cert %.3g ms %.2f" % (res.iters, res.cert_gap, res.ms))
+    assert res.converged and res.energy == e_star
+    lab = res.labels.cpu().numpy()
+    assert oracle.cut_energy(w, a, lab) == e_star
