@@ -57,6 +57,7 @@ extern "C" {
 
 /* mc_opts.flags */
 #define MC_VALIDATE 1u           /* check inputs on the device before solving */
+#define MC_PROFILE 2u            /* time every chain-sweep launch with hipEvents (mc_stats.sweep_ms) */
 
 /* mc_opts.variant */
 #define MC_VARIANT_AUTO 0        /* two-set form for 2D, product space for 3D */
@@ -76,8 +77,10 @@ typedef struct {
     int32_t check_every;  /* certificate cadence in iterations (default 1) */
     double gap_tol;       /* stop when cert = E(S) - LB(y) < gap_tol (default 1e-3) */
     int32_t variant;      /* MC_VARIANT_* */
-    float tau0;           /* labels S_tau = {x > tau}, tau in (+tau0, 0, -tau0) (default 1e-3) */
-    uint32_t flags;       /* MC_VALIDATE */
+    float tau0;           /* labels S_tau = {x > tau} for the ladder tau = tau0 * (1, 1e-1, 1e-2,
+                             1e-3, 0, -1e-3, -1e-2, -1e-1, -1); the first of least energy
+                             is returned (default 1e-3) */
+    uint32_t flags;       /* MC_VALIDATE | MC_PROFILE */
     int32_t reserved[4];
 } mc_opts;
 
@@ -90,6 +93,9 @@ typedef struct {
     double tv_gap;        /* TV duality gap at the FP32 primal estimate (diagnostic) */
     float tau_used;       /* threshold of the returned labels */
     float ms;             /* device time of the solve (hipEvent), milliseconds */
+    double sweep_ms;      /* MC_PROFILE: summed device time of the chain-sweep launches */
+    int32_t sweep_launches; /* MC_PROFILE: number of chain-sweep launches timed */
+    int32_t checks;       /* certificate evaluations performed */
 } mc_stats;
 
 /* Fill `o` with the defaults listed above. */

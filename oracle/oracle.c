@@ -546,12 +546,22 @@ static void orc_certificate(const orc_grid *g, const double *w,
 /*   (u - sum_k v_k)/r; z <- 1/2 (z + R_L R_K z); state has r*n entries.      */
 /* In both, the primal estimate is x = u - sum_j y_j (Sec. 2.3: x = w - y).   */
 /*                                                                            */
-/* Rounding readout (reading of Sec. 2.3's threshold at 0 for noisy         */
-/* iterates): S_tau = {x > tau} for tau in (+tau0, 0, -tau0); the first of  */
-/* minimal energy is kept; cert = E(S) - LB(y).                              */
+/* Rounding readout (reading of Sec. 2.1's level sets and Sec. 2.3's         */
+/* threshold at 0 for an approximate x): S_tau = {x > tau} for the ladder    */
+/* tau = +tau0, +tau0/10, +tau0/100, +tau0/1000, 0, -tau0/1000, ..., -tau0;  */
+/* the first of minimal energy is kept; cert = E(S) - LB(y).                 */
 /* Stop when (gap_tol <= 0 or cert < gap_tol) and (tv_tol <= 0 or           */
 /* tvgap < tv_tol), with at least one of them positive; else run max_iters. */
 /* ------------------------------------------------------------------------ */
+#define ORC_NTAU 9
+
+/* thresholds tau0 * (1, 1e-1, 1e-2, 1e-3, 0, -1e-3, -1e-2, -1e-1, -1) */
+void orc_tau_ladder(double tau0, double *taus)
+{
+    const double f[ORC_NTAU] = {1.0, 1e-1, 1e-2, 1e-3, 0.0, -1e-3, -1e-2, -1e-1, -1.0};
+    for (int t = 0; t < ORC_NTAU; ++t) taus[t] = tau0 * f[t];
+}
+
 typedef struct {
     int32_t iters;
     int32_t status;   /* 0 converged, 1 max_iters reached */
@@ -589,7 +599,8 @@ int orc_dr_solve(int ndim, const long *dims, const double *w,
     for (long i = 0; i < n; ++i) u[i] = -w[i];
     if (z0) memcpy(z, z0, sizeof(double) * (size_t)nz);
     double *pj[3] = {pd, pd + n, pd + 2 * n};
-    const double taus[3] = {tau0, 0.0, -tau0};
+    double taus[ORC_NTAU];
+    orc_tau_ladder(tau0, taus);
 
     int it = 0, done = 0;
     double cert = INFINITY, energy = INFINITY, lb = -INFINITY, tvgap = INFINITY, tau_used = 0;
@@ -630,7 +641,7 @@ int orc_dr_solve(int ndim, const long *dims, const double *w,
         }
         orc_certificate(&g, w, a, pj, &lb, &tvgap);
         energy = INFINITY;
-        for (int t = 0; t < 3; ++t) {
+        for (int t = 0; t < ORC_NTAU; ++t) {
             for (long i = 0; i < n; ++i) lab[i] = (uint8_t)(x[i] > taus[t]);
             double e = orc_cut_energy(ndim, dims, w, a, lab);
             if (e < energy) {

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "launch.hpp"
 #include "mc.h"
@@ -24,9 +25,10 @@ struct mc_ctx {
     float* xt = nullptr;     // n   primal estimate -w - sum_j D_j^T p_j (check iterations)
     SegRec* rec = nullptr;   // r*n segment records
     double* partials = nullptr;  // kReduceBlocks * kCertValues
-    double* dout = nullptr;      // 8 doubles
-    double* hout = nullptr;      // 8 doubles, pinned host
+    double* dout = nullptr;      // kCertValues doubles
+    double* hout = nullptr;      // kCertValues doubles, pinned host
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> prof_ev;  // MC_PROFILE: start/stop pairs of sweep launches
 };
 
 namespace {
@@ -105,6 +107,49 @@ int ensure_ws(mc_ctx* c, size_t n, int r)
     return MC_OK;
 }
 
+// MC_PROFILE: a pool of event pairs bracketing sweep launches, drained at
+// every synchronisation point of the solve.
+struct SweepTimer {
+    mc_ctx* c;
+    bool on;
+    size_t used = 0;
+    double ms = 0.0;
+    int launches = 0;
+    hipError_t begin(hipStream_t s)
+    {
+        if (!on) return hipSuccess;
+        if (used + 2 > c->prof_ev.size()) {
+            for (int k = 0; k < 2; ++k) {
+                hipEvent_t e;
+                hipError_t r = hipEventCreate(&e);
+                if (r != hipSuccess) return r;
+                c->prof_ev.push_back(e);
+            }
+        }
+        return hipEventRecord(c->prof_ev[used], s);
+    }
+    hipError_t end(hipStream_t s)
+    {
+        if (!on) return hipSuccess;
+        hipError_t r = hipEventRecord(c->prof_ev[used + 1], s);
+        used += 2;
+        ++launches;
+        return r;
+    }
+    // call after the stream has been synchronised
+    hipError_t drain()
+    {
+        for (size_t k = 0; k < used; k += 2) {
+            float t = 0.f;
+            hipError_t r = hipEventElapsedTime(&t, c->prof_ev[k], c->prof_ev[k + 1]);
+            if (r != hipSuccess) return r;
+            ms += t;
+        }
+        used = 0;
+        return hipSuccess;
+    }
+};
+
 int check_ctx(mc_ctx* c)
 {
     if (!c) return fail(MC_ERR_INVALID_ARG, "ctx is null");
@@ -158,8 +203,8 @@ int mc_ctx_create(mc_ctx** out, int device)
     mc_ctx* c = new mc_ctx();
     c->device = device;
     if (hipMalloc(&c->partials, sizeof(double) * kReduceBlocks * kCertValues) != hipSuccess ||
-        hipMalloc(&c->dout, sizeof(double) * 8) != hipSuccess ||
-        hipHostMalloc(&c->hout, sizeof(double) * 8, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&c->dout, sizeof(double) * kCertValues) != hipSuccess ||
+        hipHostMalloc(&c->hout, sizeof(double) * kCertValues, hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         (void)hipGetLastError();
         mc_ctx_destroy(c);
@@ -180,6 +225,7 @@ int mc_ctx_destroy(mc_ctx* c)
     if (c->hout) hipHostFree(c->hout);
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
+    for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
     delete c;
     return MC_OK;
 }
@@ -257,7 +303,10 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     MC_HIP(hipEventRecord(c->ev0, s));
 
     const float* pj[3] = {c->p, c->p + n, c->p + 2 * n};
-    const float taus[3] = {o.tau0, 0.f, -o.tau0};
+    SweepTimer tm{c, (o.flags & MC_PROFILE) != 0};
+    int checks = 0;
+    float taus[kNumTau];
+    tau_ladder(o.tau0, taus);
     int it = 0;
     bool converged = false;
     double cert = INFINITY, energy = INFINITY, lb = -INFINITY, tvgap = NAN;
@@ -266,27 +315,37 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
         ++it;
         const bool check = (it % o.check_every == 0) || it == o.max_iters;
         if (two_set) {
+            MC_HIP(tm.begin(s));
             MC_HIP(launch_dr2_rows(g, c->z, a[0], w, c->t, c->y, check ? c->p : nullptr, c->rec, s));
+            MC_HIP(tm.end(s));
+            MC_HIP(tm.begin(s));
             MC_HIP(launch_dr2_cols(g, c->t, a[1], c->y, c->z, check ? c->p + n : nullptr, c->rec, s));
+            MC_HIP(tm.end(s));
         } else {
+            MC_HIP(tm.begin(s));
             MC_HIP(launch_drp_sweeps(g, r - 1, c->z, a, c->y, check ? c->p : nullptr, c->rec, s));
+            MC_HIP(tm.end(s));
+            MC_HIP(tm.begin(s));
             MC_HIP(launch_drp_final(g, r, c->z, c->y, a[r - 1], w,
                                     check ? c->p + (size_t)(r - 1) * n : nullptr,
                                     c->rec + (size_t)(r - 1) * n, s));
+            MC_HIP(tm.end(s));
         }
         if (!check) continue;
+        ++checks;
         MC_HIP(launch_cert(g, w, a, pj, o.tau0, c->xt, c->partials, c->dout, s));
         MC_HIP(hipMemcpyAsync(c->hout, c->dout, kCertValues * sizeof(double), hipMemcpyDeviceToHost, s));
         MC_HIP(hipStreamSynchronize(s));
+        MC_HIP(tm.drain());
         energy = INFINITY;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < kNumTau; ++k) {
             if (c->hout[k] < energy) {
                 energy = c->hout[k];
                 tau_used = taus[k];
             }
         }
-        tvgap = c->hout[3];
-        lb = c->hout[4];
+        tvgap = c->hout[kNumTau];
+        lb = c->hout[kNumTau + 1];
         cert = energy - lb;
         if (!isfinite(cert)) return fail(MC_ERR_NUMERIC, "non-finite certificate (NaN/Inf in the state)");
         if (cert < o.gap_tol) {
@@ -309,6 +368,10 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     stats->tv_gap = tvgap;
     stats->tau_used = tau_used;
     stats->ms = ms;
+    MC_HIP(tm.drain());
+    stats->sweep_ms = tm.ms;
+    stats->sweep_launches = tm.launches;
+    stats->checks = checks;
     return stats->status;
 }
 

@@ -371,13 +371,30 @@ k_primal(Geo g, const float* __restrict__ w, Ptr3 p, float* __restrict__ xc,
     block_reduce_store<1>(v, partials + blockIdx.x);
 }
 
-// Energies of S_tau = {x > tau} for tau = +tau0, 0, -tau0 (eq. (4)) and the
+// Energies of S_t = {x > tau_t} over the threshold ladder (eq. (4)) and the
 // TV duality gap sum_e (a_e |Dx_e| - p_e Dx_e) at the rounded x (diagnostic).
-__global__ void __launch_bounds__(kReduceThreads)
-k_cut3(Geo g, const float* __restrict__ xc, const float* __restrict__ w, Ptr3 a, Ptr3 p,
-       float tau0, double* __restrict__ partials)
+// The ladder is decreasing, so x > tau_t holds exactly for t >= cnt(x) with
+// cnt(x) = #{t : x <= tau_t}; a node enters S_t for t >= cnt and an edge is
+// cut for t in [min(cnt_i, cnt_j), max(cnt_i, cnt_j)).
+struct Taus {
+    float t[kNumTau];
+};
+
+__device__ __forceinline__ int ladder_count(float x, const Taus& tz)
 {
-    double e_hi = 0.0, e_mid = 0.0, e_lo = 0.0, tvg = 0.0;
+    int c = 0;
+#pragma unroll
+    for (int t = 0; t < kNumTau; ++t) c += (x <= tz.t[t]) ? 1 : 0;
+    return c;
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, Ptr3 a, Ptr3 p,
+             Taus tz, double* __restrict__ partials)
+{
+    double e[kNumTau + 1];
+#pragma unroll
+    for (int t = 0; t <= kNumTau; ++t) e[t] = 0.0;
     const int stride = gridDim.x * kReduceThreads;
     const int st[3] = {1, g.W, g.W * g.H};
     for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
@@ -385,25 +402,26 @@ k_cut3(Geo g, const float* __restrict__ xc, const float* __restrict__ w, Ptr3 a,
         const int cc[3] = {c.x, c.y, c.d};
         const int ext[3] = {g.W, g.H, g.D};
         const float xi = xc[i];
-        const bool b0 = xi > tau0, b1 = xi > 0.f, b2 = xi > -tau0;
+        const int ci = ladder_count(xi, tz);
         const double wi = (double)w[i];
-        if (b0) e_hi += wi;
-        if (b1) e_mid += wi;
-        if (b2) e_lo += wi;
+#pragma unroll
+        for (int t = 0; t < kNumTau; ++t)
+            if (t >= ci) e[t] += wi;
         for (int j = 0; j < g.ndim; ++j) {
             if (cc[j] + 1 < ext[j]) {
                 const float xn = xc[i + st[j]];
+                const int cn = ladder_count(xn, tz);
                 const double aj = (double)a.p[j][i];
-                if (b0 != (xn > tau0)) e_hi += aj;
-                if (b1 != (xn > 0.f)) e_mid += aj;
-                if (b2 != (xn > -tau0)) e_lo += aj;
+                const int lo = ci < cn ? ci : cn, hi = ci < cn ? cn : ci;
+#pragma unroll
+                for (int t = 0; t < kNumTau; ++t)
+                    if (t >= lo && t < hi) e[t] += aj;
                 const double dx = (double)xn - (double)xi;
-                tvg += aj * fabs(dx) - (double)p.p[j][i] * dx;
+                e[kNumTau] += aj * fabs(dx) - (double)p.p[j][i] * dx;
             }
         }
     }
-    double v[4] = {e_hi, e_mid, e_lo, tvg};
-    block_reduce_store<4>(v, partials + (size_t)blockIdx.x * 4);
+    block_reduce_store<kNumTau + 1>(e, partials + (size_t)blockIdx.x * (kNumTau + 1));
 }
 
 __global__ void __launch_bounds__(kReduceThreads)
@@ -541,14 +559,18 @@ hipError_t launch_cert(const Geo& g, const float* w, const float* const* a,
         pa.p[j] = j < g.ndim ? a[j] : nullptr;
         pp.p[j] = j < g.ndim ? p[j] : nullptr;
     }
+    Taus tz;
+    tau_ladder(tau0, tz.t);
     const int nb = reduce_blocks(g.n);
     double* part_lb = partials;
     double* part_cut = partials + kReduceBlocks;
     hipLaunchKernelGGL(k_primal, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pp, xc, part_lb);
-    hipLaunchKernelGGL(k_cut3, dim3(nb), dim3(kReduceThreads), 0, s, g, xc, w, pa, pp, tau0,
+    hipLaunchKernelGGL(k_cut_ladder, dim3(nb), dim3(kReduceThreads), 0, s, g, xc, w, pa, pp, tz,
                        part_cut);
-    hipLaunchKernelGGL(k_finalize<4>, dim3(1), dim3(kReduceThreads), 0, s, part_cut, nb, out);
-    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, part_lb, nb, out + 4);
+    hipLaunchKernelGGL(k_finalize<kNumTau + 1>, dim3(1), dim3(kReduceThreads), 0, s, part_cut, nb,
+                       out);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, part_lb, nb,
+                       out + kNumTau + 1);
     return hipGetLastError();
 }
 

@@ -27,7 +27,16 @@ __host__ __device__ inline int geo_nchains(const Geo& g, int axis) { return g.n 
 
 constexpr int kReduceBlocks = 512;   // blocks of the reduction kernels (fixed: deterministic)
 constexpr int kReduceThreads = 256;
-constexpr int kCertValues = 5;       // E(+tau0), E(0), E(-tau0), TV gap, LB
+// Rounding readout: S_t = {x > tau_t} for the decreasing threshold ladder
+// tau0 * (1, 1e-1, 1e-2, 1e-3, 0, -1e-3, -1e-2, -1e-1, -1).
+constexpr int kNumTau = 9;
+constexpr int kCertValues = kNumTau + 2;  // E(S_t) for every t, TV gap, LB
+
+inline void tau_ladder(float tau0, float* taus)
+{
+    const float f[kNumTau] = {1.f, 1e-1f, 1e-2f, 1e-3f, 0.f, -1e-3f, -1e-2f, -1e-1f, -1.f};
+    for (int t = 0; t < kNumTau; ++t) taus[t] = tau0 * f[t];
+}
 
 // Standalone prox of every chain along `axis` (x = prox(v), p = clipped duals).
 hipError_t launch_prox(const Geo& g, int axis, const float* v, const float* a, float* x,
@@ -52,8 +61,8 @@ hipError_t launch_drp_final(const Geo& g, int r, float* z, const float* y, const
                             const float* w, float* p_last, SegRec* rec, hipStream_t s);
 
 // Certificate from the edge duals p: primal xc = -w - sum_j D_j^T p_j (FP32
-// out), then out[5] = {E(+tau0), E(0), E(-tau0), TV gap, LB} in FP64.
-// partials needs 5 * kReduceBlocks doubles.
+// out), then out[kCertValues] = {E(S_t) for the ladder, TV gap, LB} in FP64.
+// partials needs kCertValues * kReduceBlocks doubles.
 hipError_t launch_cert(const Geo& g, const float* w, const float* const* a,
                        const float* const* p, float tau0, float* xc, double* partials,
                        double* out, hipStream_t s);

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_PKG, "libmc.so")
 MC_OK = 0
 MC_NOT_CONVERGED = 1
 MC_VALIDATE = 1
+MC_PROFILE = 2
 VARIANT_AUTO, VARIANT_TWO_SET, VARIANT_PRODUCT = 0, 1, 2
 
 
@@ -50,7 +51,9 @@ class Stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32),
                 ("cert_gap", ctypes.c_double), ("energy", ctypes.c_double),
                 ("lower_bound", ctypes.c_double), ("tv_gap", ctypes.c_double),
-                ("tau_used", ctypes.c_float), ("ms", ctypes.c_float)]
+                ("tau_used", ctypes.c_float), ("ms", ctypes.c_float),
+                ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
+                ("checks", ctypes.c_int32)]
 
 
 _lib = None
@@ -152,6 +155,10 @@ class SolveResult:
     lower_bound: float
     tau_used: float
     ms: float
+    tv_gap: float = float("nan")
+    sweep_ms: float = 0.0
+    sweep_launches: int = 0
+    checks: int = 0
 
     @property
     def converged(self):
@@ -159,7 +166,7 @@ class SolveResult:
 
 
 def make_opts(max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
-              validate=False):
+              validate=False, profile=False):
     o = Opts()
     load_library().mc_opts_default(ctypes.byref(o))
     o.max_iters = int(max_iters)
@@ -167,13 +174,14 @@ def make_opts(max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, 
     o.gap_tol = float(gap_tol)
     o.variant = int(variant)
     o.tau0 = float(tau0)
-    o.flags = MC_VALIDATE if validate else 0
+    o.flags = (MC_VALIDATE if validate else 0) | (MC_PROFILE if profile else 0)
     return o
 
 
 def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tensor] = None,
              max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
-             validate=False, return_x=True, return_z=False, labels_out=None) -> SolveResult:
+             validate=False, return_x=True, return_z=False, labels_out=None,
+             profile=False) -> SolveResult:
     """Minimum cut of one grid by mc_tv_solve."""
     lib = load_library()
     shape = tuple(w.shape)
@@ -194,7 +202,7 @@ def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tens
     x = torch.empty(shape, dtype=torch.float32, device=w.device) if return_x else None
     z = torch.empty(nz, dtype=torch.float32, device=w.device) if return_z else None
     st = Stats()
-    o = make_opts(max_iters, check_every, gap_tol, variant, tau0, validate)
+    o = make_opts(max_iters, check_every, gap_tol, variant, tau0, validate, profile)
     rc = lib.mc_tv_solve(context(dev), ctypes.byref(_grid(shape)), wp,
                          ctypes.cast(ap, ctypes.c_void_p), z0p,
                          ctypes.c_void_p(x.data_ptr()) if x is not None else None,
@@ -203,7 +211,8 @@ def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tens
                          ctypes.byref(st), ctypes.byref(o), _stream(dev))
     _check(rc, allow_not_converged=True)
     return SolveResult(labels, x, z, st.status, st.iters, st.cert_gap, st.energy,
-                       st.lower_bound, st.tau_used, st.ms)
+                       st.lower_bound, st.tau_used, st.ms, st.tv_gap, st.sweep_ms,
+                       st.sweep_launches, st.checks)
 
 
 def tv_prox_chains(v: torch.Tensor, a_axis: torch.Tensor, axis: int, return_p=False,

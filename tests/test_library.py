@@ -65,5 +65,5 @@ def test_struct_layouts_match_header():
     from paper_1503_01563_amd import mc
     assert ctypes.sizeof(mc.Grid) == 32
     assert ctypes.sizeof(mc.Opts) == 48
-    assert ctypes.sizeof(mc.Stats) == 48
+    assert ctypes.sizeof(mc.Stats) == 64
     assert mc.Stats.ms.offset == 44 and mc.Opts.flags.offset == 24
