@@ -19,11 +19,10 @@ struct mc_ctx {
     size_t cap_n = 0;   // voxels the workspace was sized for
     int cap_r = 0;      // families the workspace was sized for
     float* z = nullptr;      // r*n splitting state
-    float* t = nullptr;      // n   (two-set: column input)
-    float* y = nullptr;      // max(1, r-1)*n  (two-set: y1; product: y_j of non-final families)
+    float* z2 = nullptr;     // r*n second state buffer (the sweeps never update in place)
+    float* y = nullptr;      // max(1, r-1)*n: row prox q1 (two-set) or q_j of non-final families
     float* p = nullptr;      // r*n edge duals (check iterations)
     float* xt = nullptr;     // n   primal estimate -w - sum_j D_j^T p_j (check iterations)
-    SegRec* rec = nullptr;   // r*n segment records
     double* partials = nullptr;  // kReduceBlocks * kCertValues
     double* dout = nullptr;      // kCertValues doubles
     double* hout = nullptr;      // kCertValues doubles, pinned host
@@ -78,10 +77,8 @@ int make_geo(const mc_grid* grid, Geo* g)
 
 void free_ws(mc_ctx* c)
 {
-    hipFree(c->z); hipFree(c->t); hipFree(c->y); hipFree(c->p); hipFree(c->xt);
-    hipFree(c->rec);
-    c->z = c->t = c->y = c->p = c->xt = nullptr;
-    c->rec = nullptr;
+    hipFree(c->z); hipFree(c->z2); hipFree(c->y); hipFree(c->p); hipFree(c->xt);
+    c->z = c->z2 = c->y = c->p = c->xt = nullptr;
     c->cap_n = 0;
     c->cap_r = 0;
 }
@@ -94,10 +91,9 @@ int ensure_ws(mc_ctx* c, size_t n, int r)
     free_ws(c);
     const size_t fb = sizeof(float);
     const int ry = rr > 1 ? rr - 1 : 1;
-    if (hipMalloc(&c->z, fb * nn * rr) != hipSuccess || hipMalloc(&c->t, fb * nn) != hipSuccess ||
+    if (hipMalloc(&c->z, fb * nn * rr) != hipSuccess || hipMalloc(&c->z2, fb * nn * rr) != hipSuccess ||
         hipMalloc(&c->y, fb * nn * ry) != hipSuccess || hipMalloc(&c->p, fb * nn * rr) != hipSuccess ||
-        hipMalloc(&c->xt, fb * nn) != hipSuccess ||
-        hipMalloc(&c->rec, sizeof(SegRec) * nn * rr) != hipSuccess) {
+        hipMalloc(&c->xt, fb * nn) != hipSuccess) {
         free_ws(c);
         (void)hipGetLastError();
         return fail(MC_ERR_NOMEM, "workspace allocation failed");
@@ -241,7 +237,7 @@ int mc_tv_prox_chains(mc_ctx* c, const mc_grid* grid, int axis, const float* v,
     if (!v || !a_axis || !x_out) return fail(MC_ERR_INVALID_ARG, "null array");
     if ((rc = ensure_ws(c, (size_t)g.n, 1))) return rc;
     hipStream_t s = (hipStream_t)stream;
-    MC_HIP(launch_prox(g, axis, v, a_axis, x_out, p_out, c->rec, s));
+    MC_HIP(launch_prox(g, axis, v, a_axis, x_out, p_out, s));
     return MC_OK;
 }
 
@@ -311,26 +307,30 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     bool converged = false;
     double cert = INFINITY, energy = INFINITY, lb = -INFINITY, tvgap = NAN;
     float tau_used = 0.f;
+    float* zc = c->z;   // current state
+    float* zn = c->z2;  // next state
     while (it < o.max_iters) {
         ++it;
         const bool check = (it % o.check_every == 0) || it == o.max_iters;
         if (two_set) {
             MC_HIP(tm.begin(s));
-            MC_HIP(launch_dr2_rows(g, c->z, a[0], w, c->t, c->y, check ? c->p : nullptr, c->rec, s));
+            MC_HIP(launch_dr2_rows(g, zc, a[0], c->y, check ? c->p : nullptr, s));
             MC_HIP(tm.end(s));
             MC_HIP(tm.begin(s));
-            MC_HIP(launch_dr2_cols(g, c->t, a[1], c->y, c->z, check ? c->p + n : nullptr, c->rec, s));
+            MC_HIP(launch_dr2_cols(g, c->y, zc, zn, w, a[1], check ? c->p + n : nullptr, s));
             MC_HIP(tm.end(s));
         } else {
             MC_HIP(tm.begin(s));
-            MC_HIP(launch_drp_sweeps(g, r - 1, c->z, a, c->y, check ? c->p : nullptr, c->rec, s));
+            MC_HIP(launch_drp_sweeps(g, r - 1, zc, a, c->y, check ? c->p : nullptr, s));
             MC_HIP(tm.end(s));
             MC_HIP(tm.begin(s));
-            MC_HIP(launch_drp_final(g, r, c->z, c->y, a[r - 1], w,
-                                    check ? c->p + (size_t)(r - 1) * n : nullptr,
-                                    c->rec + (size_t)(r - 1) * n, s));
+            MC_HIP(launch_drp_final(g, r, zc, zn, c->y, a[r - 1], w,
+                                    check ? c->p + (size_t)(r - 1) * n : nullptr, s));
             MC_HIP(tm.end(s));
         }
+        float* zt = zc;
+        zc = zn;
+        zn = zt;
         if (!check) continue;
         ++checks;
         MC_HIP(launch_cert(g, w, a, pj, o.tau0, c->xt, c->partials, c->dout, s));
@@ -356,7 +356,7 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     MC_HIP(hipEventRecord(c->ev1, s));
     MC_HIP(launch_labels(g, c->xt, tau_used, labels_out, s));
     if (x_out) MC_HIP(hipMemcpyAsync(x_out, c->xt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
-    if (z_out) MC_HIP(hipMemcpyAsync(z_out, c->z, sizeof(float) * nz, hipMemcpyDeviceToDevice, s));
+    if (z_out) MC_HIP(hipMemcpyAsync(z_out, zc, sizeof(float) * nz, hipMemcpyDeviceToDevice, s));
     MC_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
     MC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));

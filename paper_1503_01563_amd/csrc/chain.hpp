@@ -1,34 +1,38 @@
-// chain.hpp -- exact weighted 1D total-variation prox of one chain, run by one
-// GPU lane (Sec. 3.2 of the paper: the chain subproblem
+// chain.hpp -- exact weighted 1D total-variation prox of chain pieces, run by
+// one GPU lane each (Sec. 3.2 of the paper: the chain subproblem
 //     x = argmin_x 1/2 |x - v|^2 + sum_e a_e |x_{e+1} - x_e| ).
 //
-// Two passes over the chain.
+// Direct scan.  A segment [k0, k] of constant value c is feasible while every
+// edge dual inside it stays in its box: with P_e(c) = A + sum_{i=k0..e}
+// (c - v_i) the dual of edge e (A the dual of the edge left of k0),
+// |P_e(c)| <= a_e.  Each P_e increases with c, so the feasible values form an
+// interval [vmin, vmax]; umin / umax hold the dual of the newest edge at
+// c = vmin / vmax and kmin / kmax the last edge where the lower / upper bound
+// was tight.  A new element k either tightens the interval or empties it: if
+// even c = vmin pushes the dual above +a_k, the segment ends at kmin with a
+// downward jump (dual -a there); symmetrically for vmax.  The scan restarts
+// after the knot with that dual as its anchor.  The chain end is an edge of
+// weight 0 (the taut string is pinned there).  This is the direct method of
+// Condat with per-edge weights, i.e. the taut string of the paper's weighted
+// solver seen through its dual offsets.  Every restart moves k0 forward, so a
+// piece of L elements takes at most L(L+1)/2 steps.
 //
-// Scan (forward, direct method with restarts).  A segment [k0, k] of constant
-// value c is feasible while every edge dual inside it stays in its box:
-// with P_e(c) = A + sum_{i=k0..e} (c - v_i) the dual of edge e (A the dual of
-// the edge left of k0), |P_e(c)| <= a_e.  Each P_e is increasing in c, so the
-// feasible c form an interval [vmin, vmax]; umin / umax hold the dual of the
-// newest edge at c = vmin / vmax and kmin / kmax the last edge where the lower
-// / upper bound was tight.  A new element k either tightens the interval
-// (one division by the segment length) or empties it: if even c = vmin
-// pushes the dual above +a_k, the segment must end at kmin with value vmin and
-// a downward jump (dual -a there); symmetrically for vmax.  The scan then
-// restarts after the knot with that dual as the new anchor.  The chain end is
-// an edge of weight 0 (the taut string is pinned there).  This is the direct
-// method of Condat generalised to per-edge weights, equivalently the taut
-// string of the paper's weighted solver seen through its dual offsets.  Every
-// restart moves k0 forward, so the scan ends after at most m(m+1)/2 steps.
+// Segment values come from a running sum taken in FP64 relative to the first
+// element, c = vref + (S' - A -+ a_knot) / L: accurate for large offsets,
+// huge weights and long segments.  When edge duals are wanted the value is
+// kept in FP64 and the fill carries p_j = p_{j-1} + c - v_j in FP64 from the
+// segment's exact left anchor.
 //
-// Each finished segment leaves one record at its last position: the segment
-// value and its first index, plus how the segment was entered (anchor code
-// 0 = chain start, 1 = dual +a, 2 = dual -a).
-//
-// Fill (backward, one step per element in lock-step across lanes).  Walks
-// j = m-1 .. 0, fetching a record whenever it enters a new segment, hands
-// (j, c, p_j) to the caller's emitter (p_j = dual of edge (j, j+1)), and
-// carries the dual leftwards by p_{j-1} = p_j - c + v_j inside a segment (in
-// FP64), snapping to the exact anchor +-a at each knot.
+// Pieces of one chain in parallel.  Shortest paths through the tube from two
+// different start heights to the same end never cross, and once they share a
+// tube vertex they coincide.  A lane that starts inside a chain does not know
+// the dual at its start, but the dual lies in [-a, +a]: it scans twice, from
+// the lowest (L) and the highest (U) start.  The true string lies between the
+// two, so the first knot both scans emit (same position, same side) is a knot
+// of the true string, and everything after it is exact.  The lane starts an
+// overlap W before its piece; if the two scans have not met before the piece
+// begins, it moves the start further back (at the chain start the dual is 0
+// and one scan suffices).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,119 +40,139 @@
 
 namespace mc {
 
-struct alignas(16) SegRec {
-    double val;     // segment value (FP64, see chain_scan)
-    uint32_t info;  // first index (bits 0..29) | anchor code << 30
-    uint32_t pad;
-};
-
-static_assert(sizeof(SegRec) == 16, "SegRec must be 16 bytes");
-
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// F provides: float v(int k); float a(int k) (edge k, k < m-1);
-//             void put(int k, double val, uint32_t info); SegRec get(int k);
-//             double emit(int j, double c, double pj, bool last) -> p_{j-1}.
-template <class F>
-__device__ __forceinline__ void chain_scan(const F& f, int m)
+// num / den for a positive integer-valued den, to FP64 accuracy: hardware
+// reciprocal refined by two Newton steps, then one residual correction.
+__device__ __forceinline__ double div_by_len(double num, double den)
 {
-    int k0 = 0;
-    float A = 0.f;
-    uint32_t anc = 0u;
-    while (k0 < m) {
-        const float ak0 = (k0 + 1 < m) ? f.a(k0) : 0.f;
-        // Values are emitted from an FP64 running sum taken relative to the
-        // first element, c = vref + (S' - A -+ a_knot) / L.  It stays accurate
-        // for large offsets (S' small), for huge weights (where the FP32
-        // interval bounds lose the data's low bits) and over long segments;
-        // the duals rebuilt from c in the fill then drift by FP64 rounding only.
-        const float vref = f.v(k0);
-        const double vref64 = (double)vref;
-        const float v0 = vref - A;
-        float vmin = v0 - ak0, vmax = v0 + ak0;
-        float umin = -ak0, umax = ak0;
-        int kmin = k0, kmax = k0;
-        double s = 0.0, smin = 0.0, smax = 0.0;
-        int next = m;  // m: the segment runs to the chain end
-        float len = 1.f;
-        for (int k = k0 + 1; k < m; ++k) {
-            const float vk = f.v(k);
-            const float ak = (k + 1 < m) ? f.a(k) : 0.f;
-            const float pmin = umin + (vmin - vk);
-            const float pmax = umax + (vmax - vk);
-            if (pmin > ak) {
-                // even the smallest feasible value overflows edge k: knot at kmin, jump down
-                const float akn = f.a(kmin);
-                const double c = vref64 + (smin - (double)A - (double)akn) / (double)(kmin - k0 + 1);
-                f.put(kmin, c, (uint32_t)k0 | (anc << 30));
-                A = -akn;
-                anc = 2u;
-                next = kmin + 1;
-                break;
-            }
-            if (pmax < -ak) {
-                // even the largest feasible value underflows edge k: knot at kmax, jump up
-                const float akn = f.a(kmax);
-                const double c = vref64 + (smax - (double)A + (double)akn) / (double)(kmax - k0 + 1);
-                f.put(kmax, c, (uint32_t)k0 | (anc << 30));
-                A = akn;
-                anc = 1u;
-                next = kmax + 1;
-                break;
-            }
-            s += (double)vk - vref64;
-            len += 1.f;
-            const float inv = fast_rcp(len);
-            if (pmin <= -ak) {
-                vmin += (-ak - pmin) * inv;
-                umin = -ak;
-                kmin = k;
-                smin = s;
-            } else {
-                umin = pmin;
-            }
-            if (pmax >= ak) {
-                vmax -= (pmax - ak) * inv;
-                umax = ak;
-                kmax = k;
-                smax = s;
-            } else {
-                umax = pmax;
-            }
-        }
-        if (next == m) f.put(m - 1, vref64 + (s - (double)A) / (double)(m - k0), (uint32_t)k0 | (anc << 30));
-        k0 = next;
-    }
-}
-
-template <class F>
-__device__ __forceinline__ void chain_fill(F& f, int m)
-{
-    double c = 0.0;
-    int seg0 = m;
-    uint32_t anc_right = 0u;
-    double pj = 0.0;
-    for (int j = m - 1; j >= 0; --j) {
-        if (j < seg0) {
-            if (j < m - 1) {
-                const double aj = (double)f.a(j);
-                pj = anc_right == 1u ? aj : (anc_right == 2u ? -aj : 0.0);
-            } else {
-                pj = 0.0;
-            }
-            const SegRec r = f.get(j);
-            c = r.val;
-            seg0 = (int)(r.info & 0x3fffffffu);
-            anc_right = r.info >> 30;
-        }
-        pj = f.emit(j, c, pj, j == m - 1);
-    }
+    double r = __builtin_amdgcn_rcp(den);
+    r = __builtin_fma(__builtin_fma(-den, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-den, r, 1.0), r, r);
+    const double q = num * r;
+    return __builtin_fma(__builtin_fma(-den, q, num), r, q);
 }
 
 // dual clipped to its box and rounded to FP32 (|result| <= a exactly)
 __device__ __forceinline__ float clip_dual(double p, float a)
 {
     return fminf(fmaxf((float)p, -a), a);
+}
+
+// A finished segment ending at kend, of value c, entered with dual A.
+struct Seg {
+    double c;
+    float A;
+    int kend;
+};
+
+// State of one direct scan.
+struct Scan {
+    int k0, k;       // open segment start, next position to read
+    float A;         // dual of the edge left of k0 (exactly +-a or 0)
+    bool on;         // still scanning
+    float vmin, vmax, umin, umax, len;
+    int kmin, kmax;
+    float amin, amax;  // weights of the edges kmin and kmax
+    float vref;
+    double s, smin, smax;
+};
+
+__device__ __forceinline__ void scan_start(Scan& s, int k0, float A, bool on)
+{
+    s.k0 = k0;
+    s.k = k0;
+    s.A = A;
+    s.on = on;
+    s.vmin = s.vmax = s.umin = s.umax = s.vref = s.amin = s.amax = 0.f;
+    s.len = 1.f;
+    s.kmin = s.kmax = k0;
+    s.s = s.smin = s.smax = 0.0;
+}
+
+__device__ __forceinline__ void scan_open(Scan& s, float vk, float ak)
+{
+    s.vref = vk;
+    const float v0 = vk - s.A;
+    s.vmin = v0 - ak;
+    s.vmax = v0 + ak;
+    s.umin = -ak;
+    s.umax = ak;
+    s.kmin = s.kmax = s.k0;
+    s.amin = s.amax = ak;
+    s.s = s.smin = s.smax = 0.0;
+    s.len = 1.f;
+}
+
+template <bool kExact>
+__device__ __forceinline__ double seg_value(float vref, double num, int len)
+{
+    return kExact ? (double)vref + div_by_len(num, (double)len)
+                  : (double)(vref + (float)num * fast_rcp((float)len));
+}
+
+// One step at position s.k with vk = v(s.k), ak = weight of edge s.k (0 for
+// the chain's last element m-1).  Returns true and fills `out` when a segment
+// is finished.  kExact selects an FP64 segment value (needed for edge duals).
+// Written with selects rather than branches: under SIMT every branch that any
+// lane takes costs all lanes, and the state updates of the three cases (open,
+// extend, knot) are cheap next to the exec-mask bookkeeping of branches.
+template <bool kExact>
+__device__ __forceinline__ bool scan_step(Scan& s, int m, float vk, float ak, Seg& out)
+{
+    const bool opening = s.k == s.k0;
+    const bool last = s.k == m - 1;
+    const float pmin = s.umin + (s.vmin - vk);
+    const float pmax = s.umax + (s.vmax - vk);
+    const bool down = !opening && pmin > ak;  // even the smallest value overflows edge k
+    const bool up = !opening && !down && pmax < -ak;  // even the largest underflows it
+    const bool knot = down || up;
+    const bool extend = !opening && !knot;
+
+    // the segment finished by this step: [k0, kn] at a knot, [k0, m-1] at the
+    // chain end (kn = m-1, dual 0 there)
+    const int kn = down ? s.kmin : (up ? s.kmax : m - 1);
+    const float an = down ? -s.amin : (up ? s.amax : 0.f);
+    const double s_ext = s.s + ((double)vk - (double)s.vref);
+    const double sn = down ? s.smin : (up ? s.smax : (opening ? 0.0 : s_ext));
+    const float vr = opening ? vk : s.vref;
+    out.c = seg_value<kExact>(vr, sn - (double)s.A + (double)an, kn - s.k0 + 1);
+    out.A = s.A;
+    out.kend = kn;
+    const bool finished = knot || last;
+
+    // after a knot at kn the next segment starts at kn + 1: at once if that is
+    // the current element (and not the last), else by rescanning from there
+    const bool reopen = knot && kn + 1 == s.k && !last;
+    const bool rescan = knot && !reopen;
+    const bool open_now = opening || reopen;
+    const float A1 = knot ? an : s.A;
+    const int k01 = knot ? kn + 1 : s.k0;
+
+    const float len1 = s.len + 1.f;
+    const float inv = fast_rcp(len1);
+    const bool tl = extend && pmin <= -ak, tu = extend && pmax >= ak;
+    const float v0 = vk - A1;
+    s.vmin = open_now ? v0 - ak : (tl ? s.vmin + (-ak - pmin) * inv : s.vmin);
+    s.vmax = open_now ? v0 + ak : (tu ? s.vmax - (pmax - ak) * inv : s.vmax);
+    s.umin = open_now ? -ak : (tl ? -ak : pmin);
+    s.umax = open_now ? ak : (tu ? ak : pmax);
+    s.kmin = open_now ? s.k : (tl ? s.k : s.kmin);
+    s.kmax = open_now ? s.k : (tu ? s.k : s.kmax);
+    s.amin = open_now || tl ? ak : s.amin;
+    s.amax = open_now || tu ? ak : s.amax;
+    s.smin = open_now ? 0.0 : (tl ? s_ext : s.smin);
+    s.smax = open_now ? 0.0 : (tu ? s_ext : s.smax);
+    s.s = open_now ? 0.0 : (extend ? s_ext : s.s);
+    s.len = open_now ? 1.f : (extend ? len1 : s.len);
+    s.vref = open_now ? vk : s.vref;
+    s.A = A1;
+    s.k0 = k01;
+    s.on = s.on && !(last && !rescan);
+    s.k = rescan ? k01 : s.k + 1;
+    // at the last element after a knot the one-element final segment is
+    // finished by the next step (rescan from k01 = m - 1)
+    return finished;
 }
 
 }  // namespace mc

@@ -25,6 +25,15 @@ __host__ __device__ inline int geo_stride(const Geo& g, int axis)
 }
 __host__ __device__ inline int geo_nchains(const Geo& g, int axis) { return g.n / geo_extent(g, axis); }
 
+// How a family's chains are cut into pieces for the sweep kernels: pieces of
+// `len` positions (the last may be shorter), each scanned from `overlap`
+// positions earlier and past its end by up to `tail` positions from LDS.
+struct PieceCfg {
+    int len, pieces, overlap, tail;
+};
+
+PieceCfg piece_config(const Geo& g, int axis);
+
 constexpr int kReduceBlocks = 512;   // blocks of the reduction kernels (fixed: deterministic)
 constexpr int kReduceThreads = 256;
 // Rounding readout: S_t = {x > tau_t} for the decreasing threshold ladder
@@ -40,25 +49,26 @@ inline void tau_ladder(float tau0, float* taus)
 
 // Standalone prox of every chain along `axis` (x = prox(v), p = clipped duals).
 hipError_t launch_prox(const Geo& g, int axis, const float* v, const float* a, float* x,
-                       float* p, SegRec* rec, hipStream_t s);
+                       float* p, hipStream_t s);
 
-// Two-set splitting, rows: q1 = prox_rows(z); y1 = z - q1; t = -w - y1 + q1.
-hipError_t launch_dr2_rows(const Geo& g, const float* z, const float* a_x, const float* w,
-                           float* t, float* y1, float* p1, SegRec* rec, hipStream_t s);
+// Two-set splitting, rows: q1 = prox_rows(z); p1 (clipped duals) when non-null.
+hipError_t launch_dr2_rows(const Geo& g, const float* z, const float* a_x, float* q1, float* p1,
+                           hipStream_t s);
 
-// Two-set splitting, columns: q2 = prox_cols(t); z <- y1 + q2; p2 on checks.
-hipError_t launch_dr2_cols(const Geo& g, const float* t, const float* a_y, const float* y1,
-                           float* z, float* p2, SegRec* rec, hipStream_t s);
+// Two-set splitting, columns: t = q1 - (z - q1) - w, q2 = prox_cols(t),
+// znew = (z - q1) + q2; p2 when non-null.
+hipError_t launch_dr2_cols(const Geo& g, const float* q1, const float* z, float* znew,
+                           const float* w, const float* a_y, float* p2, hipStream_t s);
 
-// Product space, non-final families: y_j = z_j - prox_j(z_j) for each axis in
-// [0, nfam) (one launch); p_j written when p != nullptr.
+// Product space, non-final families 0..nfam-1 (nfam <= 2, one launch):
+// q_j = prox_j(z_j) at q + j*n; p_j at p + j*n when p != nullptr.
 hipError_t launch_drp_sweeps(const Geo& g, int nfam, const float* z, const float* const* a,
-                             float* y, float* p, SegRec* rec, hipStream_t s);
+                             float* q, float* p, hipStream_t s);
 
 // Product space, final family (axis r-1) fused with the average over L:
-// z_j <- y_j - (2Y - Z - u)/r; p_{r-1} on checks.
-hipError_t launch_drp_final(const Geo& g, int r, float* z, const float* y, const float* a_last,
-                            const float* w, float* p_last, SegRec* rec, hipStream_t s);
+// y_j = z_j - q_j, znew_j = y_j - (2Y - Z - u)/r; p_{r-1} when non-null.
+hipError_t launch_drp_final(const Geo& g, int r, const float* z, float* znew, const float* q,
+                            const float* a_last, const float* w, float* p_last, hipStream_t s);
 
 // Certificate from the edge duals p: primal xc = -w - sum_j D_j^T p_j (FP32
 // out), then out[kCertValues] = {E(S_t) for the ladder, TV gap, LB} in FP64.

@@ -1,0 +1,177 @@
+// piece.hpp -- one lane's share of a chain sweep: the chain prox restricted to
+// the piece [b0, b1) of one chain (see chain.hpp for the scan and for why a
+// piece that starts inside a chain can be solved exactly on its own).
+//
+// The lane brackets the unknown dual at its start with two scans L (start dual
+// -a) and U (start dual +a) from p0 = b0 - W.  Each scan only advances while
+// its last knot is not ahead of the other's, so the first knot they share is
+// seen when the second of them emits it.  A shared knot K < b0 makes
+// everything from K+1 on exact: U is dropped and L continues alone.  If the
+// scans pass b0 without sharing a knot, the lane restarts with a four times
+// longer overlap; from the chain start (dual 0) one scan is exact at once.
+//
+// Finished segments go to a two-entry queue; a fill trails the scan and
+// writes the outputs of positions in [b0, b1) (the dual of each edge is carried
+// in FP64 from the segment's exact left anchor when kExact).  The scan stops
+// once the segment covering b1 - 1 is finished.
+//
+// Vals(q) returns the values of position q (r[0] scan input, r[1] weight of
+// edge q); Emit(q, c, p, last) records the result of position q: segment
+// value c and dual p of edge (q, q+1) (meaningful when kExact and not last).
+#pragma once
+
+#include "chain.hpp"
+
+namespace mc {
+
+template <int NR>
+struct RingVals {
+    float r[NR];
+};
+
+template <int NR, bool kExact>
+struct PieceLane {
+    int m, b0, b1, W;
+    bool bracket;    // L and U both running
+    bool scanning;   // the piece is not determined yet
+    Scan L, U;
+    int lastL, lastU;  // position of the last knot of each scan (-1: none)
+    float ancL, ancU;  // dual of the edge at that knot
+    // fill
+    int fj, fend;  // next position to write, end of the segment being written
+    double fc, fp;  // its value, dual of the edge left of fj
+    Seg q0, q1;     // queued finished segments
+    int qn;
+
+    // (Re)start the scans from p0 = max(0, b0 - W); a_before(q) is the weight
+    // of edge q (only read when p0 > 0).
+    template <class AAt>
+    __device__ __forceinline__ void restart(const AAt& a_before)
+    {
+        const int p0 = b0 - W > 0 ? b0 - W : 0;
+        qn = 0;
+        fend = -1;
+        fc = 0.0;
+        fp = 0.0;
+        lastL = lastU = -1;
+        ancL = ancU = 0.f;
+        if (p0 == 0) {
+            bracket = false;
+            scan_start(L, 0, 0.f, true);
+            scan_start(U, 0, 0.f, false);
+            fj = 0;
+        } else {
+            const float ab = a_before(p0 - 1);
+            bracket = true;
+            scan_start(L, p0, -ab, true);
+            scan_start(U, p0, ab, true);
+            fj = m;  // no fill before the scans merge
+        }
+    }
+
+    template <class AAt>
+    __device__ __forceinline__ void begin(bool active, int m_, int b0_, int b1_, int W0,
+                                          const AAt& a_before)
+    {
+        m = m_;
+        b0 = b0_;
+        b1 = b1_;
+        W = W0;
+        scanning = active;
+        restart(a_before);
+        if (!active) {
+            L.on = U.on = false;
+            fj = m;
+        }
+    }
+
+    __device__ __forceinline__ bool fill_ready() const { return fj < b1 && (fend >= fj || qn > 0); }
+    __device__ __forceinline__ bool busy() const { return scanning || fill_ready(); }
+
+    __device__ __forceinline__ void push(bool on, const Seg& s)
+    {
+        const bool to0 = on && qn == 0, to1 = on && qn == 1;
+        q0.c = to0 ? s.c : q0.c;
+        q0.A = to0 ? s.A : q0.A;
+        q0.kend = to0 ? s.kend : q0.kend;
+        q1.c = to1 ? s.c : q1.c;
+        q1.A = to1 ? s.A : q1.A;
+        q1.kend = to1 ? s.kend : q1.kend;
+        qn += on ? 1 : 0;
+    }
+
+    // One iteration is fill(), step_l(), then -- only while some lane of the
+    // wave brackets -- step_u() and resolve().  Keeping the scans in separate
+    // calls lets a wave skip U once all its lanes have merged.
+
+    // write one position of the finished segments
+    template <class Vals, class Emit>
+    __device__ __forceinline__ void fill(const Vals& vals, const Emit& emit)
+    {
+        if (!fill_ready()) return;
+        const bool pop = fend < fj;
+        fc = pop ? q0.c : fc;
+        fp = pop ? (double)q0.A : fp;
+        fend = pop ? q0.kend : fend;
+        q0.c = pop ? q1.c : q0.c;
+        q0.A = pop ? q1.A : q0.A;
+        q0.kend = pop ? q1.kend : q0.kend;
+        qn -= pop ? 1 : 0;
+        const RingVals<NR> rv = vals(fj);
+        const double pr = kExact ? fp + (fc - (double)rv.r[0]) : 0.0;
+        if (fj >= b0) emit(fj, fc, pr, fj == m - 1);
+        fp = pr;
+        ++fj;
+    }
+
+    // advance L (the only scan once the bracket is resolved)
+    template <class Vals>
+    __device__ __forceinline__ void step_l(const Vals& vals)
+    {
+        if (!scanning || qn == 2 || (bracket && lastL > lastU)) return;
+        const int k = L.k;
+        const RingVals<NR> rv = vals(k);
+        Seg sg;
+        const bool fin = scan_step<kExact>(L, m, rv.r[0], k + 1 < m ? rv.r[1] : 0.f, sg);
+        const bool br = bracket;
+        lastL = fin && br ? sg.kend : lastL;
+        ancL = fin && br ? L.A : ancL;
+        push(fin && !br, sg);
+        scanning = scanning && !(fin && !br && sg.kend >= b1 - 1);
+    }
+
+    __device__ __forceinline__ bool needs_u() const { return scanning && bracket && lastU <= lastL; }
+
+
+    template <class Vals>
+    __device__ __forceinline__ void step_u(const Vals& vals)
+    {
+        if (!needs_u()) return;
+        const int k = U.k;
+        const RingVals<NR> rv = vals(k);
+        Seg sg;
+        const bool fin = scan_step<false>(U, m, rv.r[0], k + 1 < m ? rv.r[1] : 0.f, sg);
+        lastU = fin ? sg.kend : lastU;
+        ancU = fin ? U.A : ancU;
+    }
+
+    // after both scans stepped: merged, failed, or keep going
+    template <class AAt>
+    __device__ __forceinline__ void resolve(const AAt& a_before)
+    {
+        if (!scanning || !bracket) return;
+        if (lastL == lastU && lastL >= 0 && ancL == ancU && lastL < b0 && L.on) {
+            // merged at a knot before the piece: L is exact from here
+            bracket = false;
+            U.on = false;
+            fj = lastL + 1;
+            fend = lastL;
+        } else if ((lastL >= b0 - 1 && lastU >= b0 - 1) || !L.on || !U.on) {
+            // no shared knot before the piece: start further back
+            W *= 4;
+            restart(a_before);
+        }
+    }
+};
+
+}  // namespace mc

@@ -1,0 +1,295 @@
+// reduce.hip -- certificate, cut energy, input validation and label kernels
+// for gfx950.
+//
+// Grid-stride kernels over voxels; reductions accumulate in FP64, reduce each
+// wave with xor-shuffles, then across the block in LDS, then across blocks in
+// a single fixed-order block: results do not depend on timing.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "chain.hpp"
+#include "launch.hpp"
+
+namespace mc {
+
+namespace {
+
+// ---- reductions ---------------------------------------------------------------
+
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double* __restrict__ out)
+{
+    constexpr int kWaves = kReduceThreads / 64;
+    __shared__ double sm[NV][kWaves];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) sm[q][wv] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            double s = 0.0;
+            for (int k = 0; k < kWaves; ++k) s += sm[q][k];
+            out[q] = s;
+        }
+    }
+}
+
+// sum of nblk rows of NV partials, fixed order
+template <int NV>
+__global__ void __launch_bounds__(kReduceThreads)
+k_finalize(const double* __restrict__ partials, int nblk, double* __restrict__ out)
+{
+    double v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += kReduceThreads) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] += partials[b * NV + q];
+    }
+    block_reduce_store<NV>(v, out);
+}
+
+struct Coords {
+    int x, y, d;
+};
+
+__device__ __forceinline__ Coords coords_of(const Geo& g, int i)
+{
+    Coords c;
+    const int hw = g.H * g.W;
+    c.d = i / hw;
+    const int r = i - c.d * hw;
+    c.y = r / g.W;
+    c.x = r - c.y * g.W;
+    return c;
+}
+
+struct Ptr3 {
+    const float* p[3];
+};
+
+// Primal estimate and lower bound from the edge duals (Sec. 2.2, 2.3):
+// y = sum_j D_j^T p_j with p clipped to its box (so y lies in K exactly),
+// x = -w - y (the TV primal x = w - y in the paper's sign), and
+// LB(y) = sum_i min(y_i + w_i, 0).  Both are formed in FP64 from the FP32
+// duals, which stay bounded by the weights, unlike the diverging state.
+__global__ void __launch_bounds__(kReduceThreads)
+k_primal(Geo g, const float* __restrict__ w, Ptr3 p, float* __restrict__ xc,
+         double* __restrict__ partials)
+{
+    double lb = 0.0;
+    const int stride = gridDim.x * kReduceThreads;
+    const int st[3] = {1, g.W, g.W * g.H};
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
+        const Coords c = coords_of(g, i);
+        const int cc[3] = {c.x, c.y, c.d};
+        double y = 0.0;
+        for (int j = 0; j < g.ndim; ++j) {
+            y -= (double)p.p[j][i];  // zero on the last slice
+            if (cc[j] > 0) y += (double)p.p[j][i - st[j]];
+        }
+        const double s = y + (double)w[i];
+        if (s < 0.0) lb += s;
+        xc[i] = (float)(-s);
+    }
+    double v[1] = {lb};
+    block_reduce_store<1>(v, partials + blockIdx.x);
+}
+
+// Energies of S_t = {x > tau_t} over the threshold ladder (eq. (4)) and the
+// TV duality gap sum_e (a_e |Dx_e| - p_e Dx_e) at the rounded x (diagnostic).
+// The ladder is decreasing, so x > tau_t holds exactly for t >= cnt(x) with
+// cnt(x) = #{t : x <= tau_t}; a node enters S_t for t >= cnt and an edge is
+// cut for t in [min(cnt_i, cnt_j), max(cnt_i, cnt_j)).
+struct Taus {
+    float t[kNumTau];
+};
+
+__device__ __forceinline__ int ladder_count(float x, const Taus& tz)
+{
+    int c = 0;
+#pragma unroll
+    for (int t = 0; t < kNumTau; ++t) c += (x <= tz.t[t]) ? 1 : 0;
+    return c;
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, Ptr3 a, Ptr3 p,
+             Taus tz, double* __restrict__ partials)
+{
+    double e[kNumTau + 1];
+#pragma unroll
+    for (int t = 0; t <= kNumTau; ++t) e[t] = 0.0;
+    const int stride = gridDim.x * kReduceThreads;
+    const int st[3] = {1, g.W, g.W * g.H};
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
+        const Coords c = coords_of(g, i);
+        const int cc[3] = {c.x, c.y, c.d};
+        const int ext[3] = {g.W, g.H, g.D};
+        const float xi = xc[i];
+        const int ci = ladder_count(xi, tz);
+        const double wi = (double)w[i];
+#pragma unroll
+        for (int t = 0; t < kNumTau; ++t)
+            if (t >= ci) e[t] += wi;
+        for (int j = 0; j < g.ndim; ++j) {
+            if (cc[j] + 1 < ext[j]) {
+                const float xn = xc[i + st[j]];
+                const int cn = ladder_count(xn, tz);
+                const double aj = (double)a.p[j][i];
+                const int lo = ci < cn ? ci : cn, hi = ci < cn ? cn : ci;
+#pragma unroll
+                for (int t = 0; t < kNumTau; ++t)
+                    if (t >= lo && t < hi) e[t] += aj;
+                const double dx = (double)xn - (double)xi;
+                e[kNumTau] += aj * fabs(dx) - (double)p.p[j][i] * dx;
+            }
+        }
+    }
+    block_reduce_store<kNumTau + 1>(e, partials + (size_t)blockIdx.x * (kNumTau + 1));
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_energy(Geo g, const float* __restrict__ w, Ptr3 a, const uint8_t* __restrict__ lab,
+         double* __restrict__ partials)
+{
+    double e = 0.0;
+    const int stride = gridDim.x * kReduceThreads;
+    const int st[3] = {1, g.W, g.W * g.H};
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
+        const Coords c = coords_of(g, i);
+        const int cc[3] = {c.x, c.y, c.d};
+        const int ext[3] = {g.W, g.H, g.D};
+        const bool b = lab[i] != 0;
+        if (b) e += (double)w[i];
+        for (int j = 0; j < g.ndim; ++j) {
+            if (cc[j] + 1 < ext[j]) {
+                if (b != (lab[i + st[j]] != 0)) e += (double)a.p[j][i];
+            }
+        }
+    }
+    double v[1] = {e};
+    block_reduce_store<1>(v, partials + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_validate(Geo g, const float* __restrict__ w, Ptr3 a, double* __restrict__ partials)
+{
+    double bad_w = 0.0, nonfin = 0.0;
+    const int stride = gridDim.x * kReduceThreads;
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
+        const Coords c = coords_of(g, i);
+        const int cc[3] = {c.x, c.y, c.d};
+        const int ext[3] = {g.W, g.H, g.D};
+        if (!isfinite(w[i])) nonfin += 1.0;
+        for (int j = 0; j < g.ndim; ++j) {
+            const float aj = a.p[j][i];
+            if (!isfinite(aj)) nonfin += 1.0;
+            else if (aj < 0.f || (cc[j] + 1 == ext[j] && aj != 0.f)) bad_w += 1.0;
+        }
+    }
+    double v[2] = {bad_w, nonfin};
+    block_reduce_store<2>(v, partials + (size_t)blockIdx.x * 2);
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_count_nonfinite(const float* __restrict__ x, int n, double* __restrict__ partials)
+{
+    double c = 0.0;
+    const int stride = gridDim.x * kReduceThreads;
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < n; i += stride)
+        if (!isfinite(x[i])) c += 1.0;
+    double v[1] = {c};
+    block_reduce_store<1>(v, partials + blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_labels(int n, const float* __restrict__ xc, float tau, uint8_t* __restrict__ lab)
+{
+    const int stride = gridDim.x * kReduceThreads;
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < n; i += stride)
+        lab[i] = xc[i] > tau ? 1 : 0;
+}
+
+inline int reduce_blocks(int n)
+{
+    int b = (n + kReduceThreads - 1) / kReduceThreads;
+    return b < 1 ? 1 : (b > kReduceBlocks ? kReduceBlocks : b);
+}
+
+}  // namespace
+
+// ---- launchers ----------------------------------------------------------------
+
+hipError_t launch_cert(const Geo& g, const float* w, const float* const* a,
+                       const float* const* p, float tau0, float* xc, double* partials,
+                       double* out, hipStream_t s)
+{
+    Ptr3 pa, pp;
+    for (int j = 0; j < 3; ++j) {
+        pa.p[j] = j < g.ndim ? a[j] : nullptr;
+        pp.p[j] = j < g.ndim ? p[j] : nullptr;
+    }
+    Taus tz;
+    tau_ladder(tau0, tz.t);
+    const int nb = reduce_blocks(g.n);
+    double* part_lb = partials;
+    double* part_cut = partials + kReduceBlocks;
+    hipLaunchKernelGGL(k_primal, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pp, xc, part_lb);
+    hipLaunchKernelGGL(k_cut_ladder, dim3(nb), dim3(kReduceThreads), 0, s, g, xc, w, pa, pp, tz,
+                       part_cut);
+    hipLaunchKernelGGL(k_finalize<kNumTau + 1>, dim3(1), dim3(kReduceThreads), 0, s, part_cut, nb,
+                       out);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, part_lb, nb,
+                       out + kNumTau + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_labels(const Geo& g, const float* xc, float tau, uint8_t* labels, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_labels, dim3(reduce_blocks(g.n)), dim3(kReduceThreads), 0, s, g.n, xc,
+                       tau, labels);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy(const Geo& g, const float* w, const float* const* a,
+                         const uint8_t* labels, double* partials, double* out, hipStream_t s)
+{
+    Ptr3 pa;
+    for (int j = 0; j < 3; ++j) pa.p[j] = j < g.ndim ? a[j] : nullptr;
+    const int nb = reduce_blocks(g.n);
+    hipLaunchKernelGGL(k_energy, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pa, labels, partials);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const Geo& g, const float* w, const float* const* a,
+                           double* partials, double* out, hipStream_t s)
+{
+    Ptr3 pa;
+    for (int j = 0; j < 3; ++j) pa.p[j] = j < g.ndim ? a[j] : nullptr;
+    const int nb = reduce_blocks(g.n);
+    hipLaunchKernelGGL(k_validate, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pa, partials);
+    hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kReduceThreads), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonfinite(const float* x, int n, double* partials, double* out,
+                                  hipStream_t s)
+{
+    const int nb = reduce_blocks(n);
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(nb), dim3(kReduceThreads), 0, s, x, n, partials);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+}  // namespace mc

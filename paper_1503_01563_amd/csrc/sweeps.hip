@@ -1,0 +1,462 @@
+// sweeps.hip -- chain-prox sweeps (Sec. 3.2) and the splitting steps built on
+// them (Sec. 3.3, 4.3), for gfx950.
+//
+// Work item = one wave64 = 64 chains of one family x one piece [b0, b1) of
+// those chains (see piece.hpp).  Cutting chains into pieces multiplies the
+// lanes available to a sweep (a 1024 x 1024 grid has only 1024 chains per
+// family, 16 waves for a 256-CU GPU) at the price of an overlap W scanned
+// twice in front of each piece.
+//
+// A work item runs in three phases, with global memory touched only in the
+// first and the last:
+//   load    the region [b0 - W, b1 + T) of the 64 chains goes to LDS with
+//           coalesced loads (chains along W are loaded transposed: lanes walk
+//           the positions of one row at a time); per position the scan input
+//           v (formed on the fly by the mode, e.g. 2 q1 - z - w) and the
+//           weight a of the edge to the next position;
+//   solve   every lane runs its piece from LDS and overwrites each slot it has
+//           finished with (segment value, edge dual); positions outside the
+//           region (a longer overlap after a failed bracket, a long last
+//           segment) are read from global memory;
+//   store   the piece's results go back with coalesced accesses, combined
+//           with the mode's other arrays (e.g. z <- (z - q1) + q2).
+// No global store is in flight during the solve phase, so its occasional
+// global loads never wait for stores (on gfx9 the vector memory counter covers
+// both).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "chain.hpp"
+#include "launch.hpp"
+#include "piece.hpp"
+
+namespace mc {
+
+namespace {
+
+constexpr int kLanes = 64;        // chains per work item; one wave per workgroup
+constexpr int kPad = kLanes + 1;  // LDS row stride: spreads the transposed accesses over banks
+
+// workgroups hold exactly one wave: ordering LDS traffic among its lanes needs
+// no barrier, only a fence that keeps the compiler from moving accesses
+__device__ __forceinline__ void wave_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct Chain {
+    int base, stride;
+};
+
+__device__ __forceinline__ Chain chain_of(const Geo& g, int axis, int c)
+{
+    Chain ch;
+    if (axis == 0) {  // c = d*H + h
+        ch.base = c * g.W;
+        ch.stride = 1;
+    } else if (axis == 1) {  // c = d*W + x
+        const int d = c / g.W;
+        ch.base = d * g.H * g.W + (c - d * g.W);
+        ch.stride = g.W;
+    } else {  // c = h*W + x
+        ch.base = c;
+        ch.stride = g.H * g.W;
+    }
+    return ch;
+}
+
+// ---- modes ---------------------------------------------------------------------
+//
+// v_at(i), a_at(i)       scan input and weight of the edge (i, i+stride) at voxel i
+// pre(i) -> Pre          other inputs the results of voxel i are combined with
+// store(i, pre, c, p)    write the results of voxel i (segment value c, dual p
+//                        of its edge; p only when duals were requested)
+
+// plain prox: x = c, optional clipped duals
+struct ModeProx {
+    const float* v;
+    const float* a;
+    float* x;
+    float* p;
+    __device__ __forceinline__ float v_at(int i) const { return v[i]; }
+    __device__ __forceinline__ float a_at(int i) const { return a[i]; }
+    struct Pre {};
+    __device__ __forceinline__ Pre pre(int) const { return {}; }
+    __device__ __forceinline__ void store(int i, float c, float pd) const
+    {
+        x[i] = c;
+        if (p) p[i] = pd;
+    }
+    __device__ __forceinline__ void store(int i, const Pre&, float c, float pd) const { store(i, c, pd); }
+};
+
+// two-set form, rows: q1 = prox_rows(z)  (y1 = z - q1 is formed by the columns)
+struct ModeRows2 {
+    const float* z;
+    const float* a;
+    float* q1;
+    float* p1;
+    __device__ __forceinline__ float v_at(int i) const { return z[i]; }
+    __device__ __forceinline__ float a_at(int i) const { return a[i]; }
+    struct Pre {};
+    __device__ __forceinline__ Pre pre(int) const { return {}; }
+    __device__ __forceinline__ void store(int i, float c, float pd) const
+    {
+        q1[i] = c;
+        if (p1) p1[i] = pd;
+    }
+    __device__ __forceinline__ void store(int i, const Pre&, float c, float pd) const { store(i, c, pd); }
+};
+
+// two-set form, columns: t = u - 2 y1 + z = q1 - y1 - w with y1 = z - q1;
+// q2 = prox_cols(t); z' = y1 + q2 (Sec. 3.3 special case r = 2, reflected
+// through rows first).  z' goes to a second buffer: pieces re-read the
+// overlap and tail of their neighbours, so the state is never updated in place.
+struct ModeCols2 {
+    const float* q1;
+    const float* z;
+    float* znew;
+    const float* w;
+    const float* a;
+    float* p2;
+    __device__ __forceinline__ float v_at(int i) const
+    {
+        const float q = q1[i];
+        const float y = z[i] - q;
+        return (q - y) - w[i];
+    }
+    __device__ __forceinline__ float a_at(int i) const { return a[i]; }
+    struct Pre {
+        float y;
+    };
+    __device__ __forceinline__ Pre pre(int i) const { return {z[i] - q1[i]}; }
+    __device__ __forceinline__ void store(int i, const Pre& pr, float c, float pd) const
+    {
+        znew[i] = pr.y + c;
+        if (p2) p2[i] = pd;
+    }
+    __device__ __forceinline__ void store(int i, float c, float pd) const { store(i, pre(i), c, pd); }
+};
+
+// product space, non-final family j: q_j = prox_j(z_j)
+struct ModeSweepP {
+    const float* z;
+    const float* a;
+    float* q;
+    float* p;
+    __device__ __forceinline__ float v_at(int i) const { return z[i]; }
+    __device__ __forceinline__ float a_at(int i) const { return a[i]; }
+    struct Pre {};
+    __device__ __forceinline__ Pre pre(int) const { return {}; }
+    __device__ __forceinline__ void store(int i, float c, float pd) const
+    {
+        q[i] = c;
+        if (p) p[i] = pd;
+    }
+    __device__ __forceinline__ void store(int i, const Pre&, float c, float pd) const { store(i, c, pd); }
+};
+
+// product space, final family R-1 fused with the average step (Pi_L of
+// eq. (dualA) inside the reflection R_L): with y_j = z_j - q_j,
+// z_j' = y_j - (2 Y - Z - u) / R, Y = sum y_j, Z = sum z_j; z' goes to a
+// second buffer (see ModeCols2).
+template <int R>
+struct ModeFinalP {
+    const float* z;  // R*n, family j at j*n
+    float* znew;     // R*n
+    const float* q;  // (R-1)*n
+    const float* a;
+    const float* w;
+    float* p;
+    int n;
+    __device__ __forceinline__ float v_at(int i) const { return z[(R - 1) * n + i]; }
+    __device__ __forceinline__ float a_at(int i) const { return a[i]; }
+    struct Pre {
+        float zl, y[R - 1], sz, w;
+    };
+    __device__ __forceinline__ Pre pre(int i) const
+    {
+        Pre pr;
+        pr.zl = z[(R - 1) * n + i];
+        pr.sz = 0.f;
+#pragma unroll
+        for (int f = 0; f < R - 1; ++f) {
+            const float zf = z[f * n + i];
+            pr.y[f] = zf - q[f * n + i];
+            pr.sz += zf;
+        }
+        pr.w = w[i];
+        return pr;
+    }
+    __device__ __forceinline__ void store(int i, const Pre& pr, float c, float pd) const
+    {
+        const float yl = pr.zl - c;
+        float Y = yl;
+#pragma unroll
+        for (int f = 0; f < R - 1; ++f) Y += pr.y[f];
+        const float Z = pr.sz + pr.zl;
+        const float corr = (2.f * Y - Z + pr.w) * (1.f / (float)R);
+#pragma unroll
+        for (int f = 0; f < R - 1; ++f) znew[f * n + i] = pr.y[f] - corr;
+        znew[(R - 1) * n + i] = yl - corr;
+        if (p) p[i] = pd;
+    }
+    __device__ __forceinline__ void store(int i, float c, float pd) const { store(i, pre(i), c, pd); }
+};
+
+// ---- one work item -----------------------------------------------------------------
+
+template <class M, bool kRows, bool kExact>
+__device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, const M& mode,
+                                            const PieceCfg& cfg, float* lds)
+{
+    const int lane = threadIdx.x;
+    const int nch = geo_nchains(g, axis);
+    const int m = geo_extent(g, axis);
+    const int cg = item / cfg.pieces, s = item - cg * cfg.pieces;
+    const int c0 = cg * kLanes;
+    const int c = c0 + lane;
+    const bool valid = c < nch;
+    const Chain ch = chain_of(g, axis, valid ? c : c0);
+    const int b0 = s * cfg.len;
+    const int b1 = b0 + cfg.len < m ? b0 + cfg.len : m;
+    const int r0 = b0 - cfg.overlap > 0 ? b0 - cfg.overlap : 0;
+    const int r1 = b1 + cfg.tail < m ? b1 + cfg.tail : m;
+    const int rmax = cfg.overlap + cfg.len + cfg.tail;  // slots per chain
+    float* lv = lds;                // [slot][lane]: v, later segment value
+    float* la = lds + rmax * kPad;  // [slot][lane]: a, later edge dual
+
+    // load: kBatch independent positions (rows) in flight before any LDS write
+    constexpr int kBatch = 16;
+    if (kRows) {
+        const int nrows = nch - c0 < kLanes ? nch - c0 : kLanes;
+        for (int q = r0 + lane; q - lane < r1; q += kLanes) {
+            for (int rb = 0; rb < nrows; rb += kBatch) {
+                float vv[kBatch], aa[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int rr = rb + u;
+                    if (rr < nrows && q < r1) {
+                        const int i = (c0 + rr) * g.W + q;
+                        vv[u] = mode.v_at(i);
+                        aa[u] = mode.a_at(i);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int rr = rb + u;
+                    if (rr < nrows && q < r1) {
+                        lv[(q - r0) * kPad + rr] = vv[u];
+                        la[(q - r0) * kPad + rr] = aa[u];
+                    }
+                }
+            }
+        }
+    } else if (valid) {
+        for (int qb = r0; qb < r1; qb += kBatch) {
+            float vv[kBatch], aa[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int q = qb + u;
+                if (q < r1) {
+                    const int i = ch.base + q * ch.stride;
+                    vv[u] = mode.v_at(i);
+                    aa[u] = mode.a_at(i);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int q = qb + u;
+                if (q < r1) {
+                    lv[(q - r0) * kPad + lane] = vv[u];
+                    la[(q - r0) * kPad + lane] = aa[u];
+                }
+            }
+        }
+    }
+    wave_fence();
+
+    // solve
+    auto vals = [&](int q) -> RingVals<2> {
+        if (q >= r0 && q < r1) return {{lv[(q - r0) * kPad + lane], la[(q - r0) * kPad + lane]}};
+        const int i = ch.base + q * ch.stride;
+        return {{mode.v_at(i), mode.a_at(i)}};
+    };
+    auto a_before = [&](int q) -> float {
+        return (q >= r0 && q < r1) ? la[(q - r0) * kPad + lane] : mode.a_at(ch.base + q * ch.stride);
+    };
+    auto emit = [&](int q, double cv, double pr, bool last) {
+        const int sl = (q - r0) * kPad + lane;
+        lv[sl] = (float)cv;
+        if (kExact) la[sl] = last ? 0.f : clip_dual(pr, la[sl]);
+    };
+    PieceLane<2, kExact> pl;
+    pl.begin(valid, m, b0, b1, cfg.overlap > 0 ? cfg.overlap : 1, a_before);
+    while (__any(pl.busy())) {
+        pl.fill(vals, emit);
+        pl.step_l(vals);
+        if (__any(pl.bracket && pl.scanning)) {
+            pl.step_u(vals);
+            pl.resolve(a_before);
+        }
+    }
+    wave_fence();
+
+    // store
+    if (kRows) {
+        const int nrows = nch - c0 < kLanes ? nch - c0 : kLanes;
+        for (int q = b0 + lane; q - lane < b1; q += kLanes) {
+            if (q < b1) {
+                for (int rr = 0; rr < nrows; ++rr)
+                    mode.store((c0 + rr) * g.W + q, lv[(q - r0) * kPad + rr],
+                               kExact ? la[(q - r0) * kPad + rr] : 0.f);
+            }
+        }
+    } else if (valid) {
+        for (int qb = b0; qb < b1; qb += kBatch) {
+            float cv[kBatch], pv[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int q = qb + u;
+                cv[u] = q < b1 ? lv[(q - r0) * kPad + lane] : 0.f;
+                pv[u] = (kExact && q < b1) ? la[(q - r0) * kPad + lane] : 0.f;
+            }
+            typename M::Pre pre[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int q = qb + u;
+                if (q < b1) pre[u] = mode.pre(ch.base + q * ch.stride);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int q = qb + u;
+                if (q < b1) mode.store(ch.base + q * ch.stride, pre[u], cv[u], pv[u]);
+            }
+        }
+    }
+}
+
+template <class M, bool kRows, bool kExact>
+__global__ void __launch_bounds__(kLanes) k_sweep(Geo g, int axis, M mode, PieceCfg cfg)
+{
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    sweep_piece<M, kRows, kExact>(g, axis, blockIdx.x, mode, cfg, lds);
+}
+
+// the two non-final families of the 3D product space in one launch:
+// items [0, n0) sweep the rows (axis 0), the rest the columns (axis 1)
+template <bool kExact>
+__global__ void __launch_bounds__(kLanes)
+k_sweep_pair(Geo g, ModeSweepP m0, ModeSweepP m1, PieceCfg c0, PieceCfg c1, int n0)
+{
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    if ((int)blockIdx.x < n0)
+        sweep_piece<ModeSweepP, true, kExact>(g, 0, blockIdx.x, m0, c0, lds);
+    else
+        sweep_piece<ModeSweepP, false, kExact>(g, 1, blockIdx.x - n0, m1, c1, lds);
+}
+
+inline int items_of(const Geo& g, int axis, const PieceCfg& cfg)
+{
+    return (geo_nchains(g, axis) + kLanes - 1) / kLanes * cfg.pieces;
+}
+
+inline size_t lds_bytes(const PieceCfg& cfg)
+{
+    return sizeof(float) * 2 * (size_t)(cfg.overlap + cfg.len + cfg.tail) * kPad;
+}
+
+template <class M, bool kExact>
+hipError_t launch_mode_x(const Geo& g, int axis, const M& mode, const PieceCfg& cfg, hipStream_t s)
+{
+    const dim3 grid(items_of(g, axis, cfg)), block(kLanes);
+    if (axis == 0)
+        hipLaunchKernelGGL((k_sweep<M, true, kExact>), grid, block, lds_bytes(cfg), s, g, axis, mode, cfg);
+    else
+        hipLaunchKernelGGL((k_sweep<M, false, kExact>), grid, block, lds_bytes(cfg), s, g, axis, mode, cfg);
+    return hipGetLastError();
+}
+
+template <class M>
+hipError_t launch_mode(const Geo& g, int axis, const M& mode, bool duals, hipStream_t s)
+{
+    const PieceCfg cfg = piece_config(g, axis);
+    return duals ? launch_mode_x<M, true>(g, axis, mode, cfg, s)
+                 : launch_mode_x<M, false>(g, axis, mode, cfg, s);
+}
+
+}  // namespace
+
+PieceCfg piece_config(const Geo& g, int axis)
+{
+    // enough work items to give every SIMD a few waves, pieces of at least 16
+    const int m = geo_extent(g, axis);
+    const int groups = (geo_nchains(g, axis) + kLanes - 1) / kLanes;
+    const int want = 4096;
+    int pieces = (want + groups - 1) / groups;
+    int len = (m + pieces - 1) / pieces;
+    len = len < 16 ? 16 : ((len + 15) / 16) * 16;
+    PieceCfg cfg;
+    cfg.len = len < m ? len : m;
+    cfg.pieces = (m + cfg.len - 1) / cfg.len;
+    cfg.overlap = cfg.pieces > 1 ? 8 : 0;
+    cfg.tail = cfg.pieces > 1 ? 8 : 0;
+    return cfg;
+}
+
+hipError_t launch_prox(const Geo& g, int axis, const float* v, const float* a, float* x, float* p,
+                       hipStream_t s)
+{
+    ModeProx m{v, a, x, p};
+    return launch_mode(g, axis, m, p != nullptr, s);
+}
+
+hipError_t launch_dr2_rows(const Geo& g, const float* z, const float* a_x, float* q1, float* p1,
+                           hipStream_t s)
+{
+    ModeRows2 m{z, a_x, q1, p1};
+    return launch_mode(g, 0, m, p1 != nullptr, s);
+}
+
+hipError_t launch_dr2_cols(const Geo& g, const float* q1, const float* z, float* znew,
+                           const float* w, const float* a_y, float* p2, hipStream_t s)
+{
+    ModeCols2 m{q1, z, znew, w, a_y, p2};
+    return launch_mode(g, 1, m, p2 != nullptr, s);
+}
+
+hipError_t launch_drp_sweeps(const Geo& g, int nfam, const float* z, const float* const* a,
+                             float* q, float* p, hipStream_t s)
+{
+    const size_t n = (size_t)g.n;
+    ModeSweepP m0{z, a[0], q, p};
+    if (nfam == 1) return launch_mode(g, 0, m0, p != nullptr, s);
+    if (nfam != 2) return hipErrorInvalidValue;
+    ModeSweepP m1{z + n, a[1], q + n, p ? p + n : nullptr};
+    const PieceCfg c0 = piece_config(g, 0), c1 = piece_config(g, 1);
+    const int n0 = items_of(g, 0, c0), n1 = items_of(g, 1, c1);
+    const size_t shm = lds_bytes(c0) > lds_bytes(c1) ? lds_bytes(c0) : lds_bytes(c1);
+    if (p)
+        hipLaunchKernelGGL(k_sweep_pair<true>, dim3(n0 + n1), dim3(kLanes), shm, s, g, m0, m1, c0, c1, n0);
+    else
+        hipLaunchKernelGGL(k_sweep_pair<false>, dim3(n0 + n1), dim3(kLanes), shm, s, g, m0, m1, c0, c1, n0);
+    return hipGetLastError();
+}
+
+hipError_t launch_drp_final(const Geo& g, int r, const float* z, float* znew, const float* q,
+                            const float* a_last, const float* w, float* p_last, hipStream_t s)
+{
+    if (r == 2) {
+        ModeFinalP<2> m{z, znew, q, a_last, w, p_last, g.n};
+        return launch_mode(g, 1, m, p_last != nullptr, s);
+    }
+    if (r == 3) {
+        ModeFinalP<3> m{z, znew, q, a_last, w, p_last, g.n};
+        return launch_mode(g, 2, m, p_last != nullptr, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace mc
