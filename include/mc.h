@@ -81,7 +81,7 @@ typedef struct {
                              1e-3, 0, -1e-3, -1e-2, -1e-1, -1); the first of least energy
                              is returned (default 1e-3) */
     uint32_t flags;       /* MC_VALIDATE | MC_PROFILE */
-    int32_t reserved[4];
+    int32_t reserved[4];  /* reserved[0]: work items per sweep launch of batched solves (0 = tuned) */
 } mc_opts;
 
 typedef struct {
@@ -96,6 +96,8 @@ typedef struct {
     double sweep_ms;      /* MC_PROFILE: summed device time of the chain-sweep launches */
     int32_t sweep_launches; /* MC_PROFILE: number of chain-sweep launches timed */
     int32_t checks;       /* certificate evaluations performed */
+    int32_t items;        /* batched solves: work items per sweep launch used */
+    int32_t reserved2;
 } mc_stats;
 
 /* Fill `o` with the defaults listed above. */
@@ -147,6 +149,27 @@ int mc_tv_prox_chains(mc_ctx *ctx, const mc_grid *grid, int axis,
 int mc_cut_energy(mc_ctx *ctx, const mc_grid *grid, const float *w,
                   const float *const *a, const uint8_t *labels,
                   double *energy_out, void *stream);
+
+/*
+ * mc_tv_solve_batched -- minimum cuts of n_grids 2D grids of possibly different
+ * sizes, solved together (two-set form).  Arrays are per grid:
+ *   grids[g]       2D grid {H, W}.
+ *   w[g]           [n_g] unaries (device).
+ *   a[2g], a[2g+1] [n_g] weights along W and along H (device).
+ *   labels[g]      [n_g] uint8 output (device).
+ *   x_out          nullable host array; x_out[g] nullable [n_g] primal estimate.
+ *   stats[g]       host; ms is the device time from the start of the solve to
+ *                  the check that certified the grid (per-grid solve time).
+ * opts.check_every is rounded up to an even number of iterations: one check
+ * period is captured in a hipGraph and replayed.  opts.reserved[0] > 0 fixes
+ * the work items per sweep launch; 0 uses the value tuned on the first solve
+ * of this batch shape.  Synchronises the stream.  Returns MC_OK when every
+ * grid is certified, MC_NOT_CONVERGED otherwise.
+ */
+int mc_tv_solve_batched(mc_ctx *ctx, int n_grids, const mc_grid *grids,
+                        const float *const *w, const float *const *a,
+                        uint8_t *const *labels, float *const *x_out, mc_stats *stats,
+                        const mc_opts *opts, void *stream);
 
 /* Text for a status code, and the calling thread's last error message. */
 const char *mc_status_string(int code);

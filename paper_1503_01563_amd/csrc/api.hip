@@ -9,48 +9,29 @@
 #include <string>
 #include <vector>
 
+#include "ctx.hpp"
 #include "launch.hpp"
 #include "mc.h"
 
 using namespace mc;
 
-struct mc_ctx {
-    int device = 0;
-    size_t cap_n = 0;   // voxels the workspace was sized for
-    int cap_r = 0;      // families the workspace was sized for
-    float* z = nullptr;      // r*n splitting state
-    float* z2 = nullptr;     // r*n second state buffer (the sweeps never update in place)
-    float* y = nullptr;      // max(1, r-1)*n: row prox q1 (two-set) or q_j of non-final families
-    float* p = nullptr;      // r*n edge duals (check iterations)
-    float* xt = nullptr;     // n   primal estimate -w - sum_j D_j^T p_j (check iterations)
-    double* partials = nullptr;  // kReduceBlocks * kCertValues
-    double* dout = nullptr;      // kCertValues doubles
-    double* hout = nullptr;      // kCertValues doubles, pinned host
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    std::vector<hipEvent_t> prof_ev;  // MC_PROFILE: start/stop pairs of sweep launches
-};
-
-namespace {
+namespace mc {
 
 thread_local std::string g_last_error;
 
-int fail(int code, const std::string& msg)
+int set_error(int code, const std::string& msg)
 {
     g_last_error = msg;
     return code;
 }
 
-int hip_fail(hipError_t e, const char* where)
-{
-    std::string m = std::string(where) + ": " + hipGetErrorString(e);
-    return fail(MC_ERR_DEVICE, m);
-}
+}  // namespace mc
 
-#define MC_HIP(call)                                  \
-    do {                                              \
-        hipError_t e_ = (call);                       \
-        if (e_ != hipSuccess) return hip_fail(e_, #call); \
-    } while (0)
+namespace {
+
+int fail(int code, const std::string& msg) { return set_error(code, msg); }
+
+int hip_fail(hipError_t e, const char* where) { return hip_error(e, where); }
 
 int make_geo(const mc_grid* grid, Geo* g)
 {
@@ -201,7 +182,8 @@ int mc_ctx_create(mc_ctx** out, int device)
     if (hipMalloc(&c->partials, sizeof(double) * kReduceBlocks * kCertValues) != hipSuccess ||
         hipMalloc(&c->dout, sizeof(double) * kCertValues) != hipSuccess ||
         hipHostMalloc(&c->hout, sizeof(double) * kCertValues, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->bstream, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
         mc_ctx_destroy(c);
         return fail(MC_ERR_NOMEM, "context allocation failed");
@@ -222,6 +204,9 @@ int mc_ctx_destroy(mc_ctx* c)
     if (c->ev0) hipEventDestroy(c->ev0);
     if (c->ev1) hipEventDestroy(c->ev1);
     for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
+    hipFree(c->bbuf);
+    hipFree(c->bmeta);
+    if (c->bstream) hipStreamDestroy(c->bstream);
     delete c;
     return MC_OK;
 }

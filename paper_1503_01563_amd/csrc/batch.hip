@@ -1,0 +1,352 @@
+// batch.hip -- mc_tv_solve_batched: minimum cuts of many 2D grids of uneven
+// sizes at once (two-set form of the splitting, Sec. 3.3).
+//
+// All grids share each launch: a sweep launch covers the row (or column)
+// pieces of every unfinished grid, a reduction launch the certificate terms of
+// every unfinished grid, and a per-grid finalize marks a grid done on the
+// device once its certificate is below the tolerance (with the iteration and
+// a wall-clock stamp), after which its work items return at once.  One check
+// period (an even number of iterations, the last one writing duals, then the
+// certificate) is captured in a hipGraph and replayed; the host looks at the
+// done flags once per replay.
+//
+// The split of chains into pieces (work items per launch) is chosen on the
+// first solve of a batch shape: the first iterations run with each candidate
+// and the fastest is kept for this shape.  The iterates do not depend on the
+// split (every piece is solved exactly), so tuning costs no extra work.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "ctx.hpp"
+#include "launch.hpp"
+#include "mc.h"
+
+using namespace mc;
+
+namespace {
+
+constexpr size_t kAlignFloats = 64;
+constexpr int kVoxelsPerRedBlock = kReduceThreads * 8;
+constexpr int kMaxRedBlocksPerGrid = 256;
+const int kCandidates[] = {2048, 4096, 8192, 16384};
+constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
+
+size_t align_floats(size_t x) { return (x + kAlignFloats - 1) / kAlignFloats * kAlignFloats; }
+size_t align_bytes(size_t x) { return (x + 255) / 256 * 256; }
+
+struct Plan {
+    std::vector<BatchGrid> tab;
+    std::vector<int> item_r, item_c, blk;
+    size_t lds_r = 0, lds_c = 0;
+};
+
+void plan_pieces(Plan& pl, const std::vector<Geo>& geos, size_t n_total, int want_total)
+{
+    pl.item_r.clear();
+    pl.item_c.clear();
+    pl.lds_r = pl.lds_c = 0;
+    for (size_t gi = 0; gi < geos.size(); ++gi) {
+        const Geo& g = geos[gi];
+        int want = (int)((double)want_total * (double)g.n / (double)n_total + 0.5);
+        if (want < 1) want = 1;
+        BatchGrid& t = pl.tab[gi];
+        t.cr = piece_config(g, 0, want);
+        t.cc = piece_config(g, 1, want);
+        const int groups_r = (geo_nchains(g, 0) + 63) / 64, groups_c = (geo_nchains(g, 1) + 63) / 64;
+        t.item0_r = (int)pl.item_r.size();
+        pl.item_r.insert(pl.item_r.end(), (size_t)groups_r * t.cr.pieces, (int)gi);
+        t.item0_c = (int)pl.item_c.size();
+        pl.item_c.insert(pl.item_c.end(), (size_t)groups_c * t.cc.pieces, (int)gi);
+        pl.lds_r = std::max(pl.lds_r, piece_lds_bytes(t.cr));
+        pl.lds_c = std::max(pl.lds_c, piece_lds_bytes(t.cc));
+    }
+}
+
+// Device metadata: a fixed header (start stamp, iteration counter), then the
+// table, the item and block maps and the reduction partials of a plan.
+constexpr size_t kHeader = 256;
+
+size_t plan_bytes(const Plan& pl, size_t* o_ir, size_t* o_ic, size_t* o_bk, size_t* o_pa)
+{
+    const size_t o_tab = kHeader;
+    *o_ir = align_bytes(o_tab + pl.tab.size() * sizeof(BatchGrid));
+    *o_ic = align_bytes(*o_ir + pl.item_r.size() * sizeof(int));
+    *o_bk = align_bytes(*o_ic + pl.item_c.size() * sizeof(int));
+    *o_pa = align_bytes(*o_bk + pl.blk.size() * sizeof(int));
+    return align_bytes(*o_pa + pl.blk.size() * kCertValues * sizeof(double));
+}
+
+int reserve_meta(mc_ctx* c, size_t total, hipStream_t s)
+{
+    if (total <= c->bmeta_cap) return MC_OK;
+    MC_HIP(hipStreamSynchronize(s));
+    hipFree(c->bmeta);
+    c->bmeta = nullptr;
+    c->bmeta_cap = 0;
+    if (hipMalloc(&c->bmeta, total) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(MC_ERR_NOMEM, "batch table allocation failed");
+    }
+    c->bmeta_cap = total;
+    return MC_OK;
+}
+
+// device copy of a plan (metadata already reserved); fills the launch descriptor
+int upload(mc_ctx* c, const Plan& pl, hipStream_t s, BatchLaunch* bl, double** partials)
+{
+    size_t o_ir, o_ic, o_bk, o_pa;
+    const size_t total = plan_bytes(pl, &o_ir, &o_ic, &o_bk, &o_pa);
+    if (total > c->bmeta_cap) return set_error(MC_ERR_DEVICE, "batch metadata not reserved");
+    char* b = c->bmeta;
+    MC_HIP(hipMemcpyAsync(b + kHeader, pl.tab.data(), pl.tab.size() * sizeof(BatchGrid), hipMemcpyHostToDevice, s));
+    MC_HIP(hipMemcpyAsync(b + o_ir, pl.item_r.data(), pl.item_r.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    MC_HIP(hipMemcpyAsync(b + o_ic, pl.item_c.data(), pl.item_c.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    MC_HIP(hipMemcpyAsync(b + o_bk, pl.blk.data(), pl.blk.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    // the host vectors are pageable and change with the next plan
+    MC_HIP(hipStreamSynchronize(s));
+    bl->tab = reinterpret_cast<BatchGrid*>(b + kHeader);
+    bl->item_grid_r = reinterpret_cast<const int*>(b + o_ir);
+    bl->item_grid_c = reinterpret_cast<const int*>(b + o_ic);
+    bl->blk_grid = reinterpret_cast<const int*>(b + o_bk);
+    bl->n_grids = (int)pl.tab.size();
+    bl->items_r = (int)pl.item_r.size();
+    bl->items_c = (int)pl.item_c.size();
+    bl->blocks = (int)pl.blk.size();
+    bl->lds_r = pl.lds_r;
+    bl->lds_c = pl.lds_c;
+    *partials = reinterpret_cast<double*>(b + o_pa);
+    return MC_OK;
+}
+
+unsigned long long signature(const std::vector<Geo>& geos)
+{
+    unsigned long long h = 1469598103934665603ull;
+    auto mix = [&](unsigned long long v) {
+        h ^= v;
+        h *= 1099511628211ull;
+    };
+    mix(geos.size());
+    for (const Geo& g : geos) {
+        mix((unsigned long long)g.H);
+        mix((unsigned long long)g.W);
+    }
+    return h;
+}
+
+}  // namespace
+
+extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
+                                   const float* const* w, const float* const* a,
+                                   uint8_t* const* labels, float* const* x_out, mc_stats* stats,
+                                   const mc_opts* opts_in, void* stream)
+{
+    if (!c) return set_error(MC_ERR_INVALID_ARG, "ctx is null");
+    MC_HIP(hipSetDevice(c->device));
+    if (n_grids < 1 || !grids || !w || !a || !labels || !stats)
+        return set_error(MC_ERR_INVALID_ARG, "null argument or n_grids < 1");
+    mc_opts o;
+    if (opts_in) o = *opts_in; else mc_opts_default(&o);
+    if (o.max_iters < 1 || o.check_every < 1) return set_error(MC_ERR_INVALID_ARG, "max_iters and check_every must be >= 1");
+    if (o.variant == MC_VARIANT_PRODUCT) return set_error(MC_ERR_INVALID_ARG, "batched solves use the two-set form");
+    const int K = (o.check_every + 1) / 2 * 2;  // iterations per replay, even: the state parity repeats
+
+    std::vector<Geo> geos((size_t)n_grids);
+    size_t n_total = 0, floats = 0;
+    for (int gi = 0; gi < n_grids; ++gi) {
+        const mc_grid& gr = grids[gi];
+        if (gr.ndim != 2 || gr.dims[0] <= 0 || gr.dims[1] <= 0)
+            return set_error(MC_ERR_INVALID_ARG, "batched grids must be 2D with positive dims");
+        if (gr.dims[0] * gr.dims[1] > INT32_MAX || gr.dims[0] >= (1 << 30) || gr.dims[1] >= (1 << 30))
+            return set_error(MC_ERR_INVALID_ARG, "grid too large");
+        if (!w[gi] || !a[2 * gi] || !a[2 * gi + 1] || !labels[gi])
+            return set_error(MC_ERR_INVALID_ARG, "null array for a grid");
+        Geo& g = geos[gi];
+        g.D = 1;
+        g.H = (int)gr.dims[0];
+        g.W = (int)gr.dims[1];
+        g.n = g.H * g.W;
+        g.ndim = 2;
+        n_total += (size_t)g.n;
+        floats += 6 * align_floats((size_t)g.n);
+    }
+    hipStream_t us = (hipStream_t)stream;
+    hipStream_t s = c->bstream;
+    if (floats > c->bcap) {
+        MC_HIP(hipDeviceSynchronize());
+        hipFree(c->bbuf);
+        c->bbuf = nullptr;
+        c->bcap = 0;
+        if (hipMalloc(&c->bbuf, floats * sizeof(float)) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(MC_ERR_NOMEM, "batch workspace allocation failed");
+        }
+        c->bcap = floats;
+    }
+
+    // per-grid table, reduction blocks
+    Plan pl;
+    pl.tab.resize((size_t)n_grids);
+    size_t off = 0;
+    for (int gi = 0; gi < n_grids; ++gi) {
+        BatchGrid& t = pl.tab[gi];
+        memset(&t, 0, sizeof(t));
+        const Geo& g = geos[gi];
+        const size_t na = align_floats((size_t)g.n);
+        t.g = g;
+        t.w = w[gi];
+        t.ax = a[2 * gi];
+        t.ay = a[2 * gi + 1];
+        t.z[0] = c->bbuf + off;
+        t.z[1] = c->bbuf + off + na;
+        t.q1 = c->bbuf + off + 2 * na;
+        t.p = c->bbuf + off + 3 * na;  // 2 * na: row duals at p, column duals at p + n
+        t.xc = c->bbuf + off + 5 * na;
+        off += 6 * na;
+        t.labels = labels[gi];
+        t.x_out = x_out ? x_out[gi] : nullptr;
+        int nb = (g.n + kVoxelsPerRedBlock - 1) / kVoxelsPerRedBlock;
+        nb = std::max(1, std::min(nb, kMaxRedBlocksPerGrid));
+        t.blk0 = (int)pl.blk.size();
+        t.nblk = nb;
+        pl.blk.insert(pl.blk.end(), (size_t)nb, gi);
+    }
+
+    // start after the caller's pending work
+    hipEvent_t ev_in = c->ev0, ev_out = c->ev1;
+    MC_HIP(hipEventRecord(ev_in, us));
+    MC_HIP(hipStreamWaitEvent(s, ev_in, 0));
+    for (int gi = 0; gi < n_grids; ++gi)
+        MC_HIP(hipMemsetAsync(pl.tab[gi].z[0], 0, sizeof(float) * (size_t)geos[gi].n, s));
+
+    const unsigned long long sig = signature(geos);
+    int items = o.reserved[0] > 0 ? o.reserved[0] : 0;
+    auto it_tuned = c->tuned_items.find(sig);
+    if (items == 0 && it_tuned != c->tuned_items.end()) items = it_tuned->second;
+
+    // metadata for the largest plan that may be used, header first
+    std::vector<int> cands;
+    if (items == 0) cands.assign(kCandidates, kCandidates + kNumCandidates);
+    else cands.push_back(items);
+    size_t need = 0;
+    for (int cand : cands) {
+        plan_pieces(pl, geos, n_total, cand);
+        size_t a1, a2, a3, a4;
+        need = std::max(need, plan_bytes(pl, &a1, &a2, &a3, &a4));
+    }
+    int rc;
+    if ((rc = reserve_meta(c, need, s))) return rc;
+    unsigned long long* t0_dev = reinterpret_cast<unsigned long long*>(c->bmeta);
+    int* iter_dev = reinterpret_cast<int*>(c->bmeta + 64);
+    MC_HIP(launch_stamp(t0_dev, s));
+
+    BatchLaunch bl;
+    double* partials = nullptr;
+    int it = 0;  // iterations done
+    if (items == 0) {
+        // autotune on the first iterations of the solve itself
+        float best_ms = INFINITY;
+        int best = kCandidates[0];
+        for (int k = 0; k < kNumCandidates && it + 1 < o.max_iters; ++k) {
+            plan_pieces(pl, geos, n_total, kCandidates[k]);
+            if ((rc = upload(c, pl, s, &bl, &partials))) return rc;
+            MC_HIP(hipEventRecord(c->ev0, s));
+            MC_HIP(launch_batch_iteration(bl, it & 1, false, s));
+            MC_HIP(hipEventRecord(c->ev1, s));
+            MC_HIP(hipEventSynchronize(c->ev1));
+            float ms = 0.f;
+            MC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = kCandidates[k];
+            }
+            ++it;
+        }
+        if (it & 1) {  // keep an even iteration count before the graph
+            MC_HIP(launch_batch_iteration(bl, it & 1, false, s));
+            ++it;
+        }
+        items = best;
+        c->tuned_items[sig] = best;
+    }
+    plan_pieces(pl, geos, n_total, items);
+    if ((rc = upload(c, pl, s, &bl, &partials))) return rc;
+
+    // one check period as a graph: K iterations, the last with duals, then the certificate
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    MC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    hipError_t cap = hipSuccess;
+    for (int j = 0; j < K && cap == hipSuccess; ++j) cap = launch_batch_iteration(bl, j & 1, j == K - 1, s);
+    if (cap == hipSuccess) cap = launch_batch_check(bl, o.tau0, o.gap_tol, iter_dev, partials, s);
+    hipError_t endc = hipStreamEndCapture(s, &graph);
+    if (cap != hipSuccess) return hip_error(cap, "batch graph capture");
+    if (endc != hipSuccess) return hip_error(endc, "hipStreamEndCapture");
+    MC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+
+    std::vector<BatchGrid> host_tab((size_t)n_grids);
+    bool all_done = false;
+    int graph_err = MC_OK;
+    while (it < o.max_iters && !all_done) {
+        if (launch_set_int(iter_dev, it + K, s) != hipSuccess || hipGraphLaunch(exec, s) != hipSuccess) {
+            graph_err = hip_error(hipGetLastError(), "batch graph replay");
+            break;
+        }
+        it += K;
+        if (hipMemcpyAsync(host_tab.data(), bl.tab, host_tab.size() * sizeof(BatchGrid),
+                           hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            graph_err = hip_error(hipGetLastError(), "batch status read");
+            break;
+        }
+        all_done = true;
+        for (const BatchGrid& t : host_tab) all_done = all_done && t.done;
+    }
+    hipGraphExecDestroy(exec);
+    hipGraphDestroy(graph);
+    if (graph_err) return graph_err;
+
+    MC_HIP(launch_batch_labels(bl, o.tau0, s));
+    unsigned long long t0 = 0;
+    MC_HIP(hipMemcpyAsync(host_tab.data(), bl.tab, host_tab.size() * sizeof(BatchGrid), hipMemcpyDeviceToHost, s));
+    MC_HIP(hipMemcpyAsync(&t0, t0_dev, sizeof(t0), hipMemcpyDeviceToHost, s));
+    unsigned long long t_end = 0;
+    MC_HIP(hipStreamSynchronize(s));
+    {
+        // end stamp for grids that did not converge
+        MC_HIP(launch_stamp(t0_dev, s));
+        MC_HIP(hipMemcpyAsync(&t_end, t0_dev, sizeof(t_end), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+    }
+    int rate_khz = 0;
+    MC_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, c->device));
+    float taus[kNumTau];
+    tau_ladder(o.tau0, taus);
+    bool ok = true;
+    for (int gi = 0; gi < n_grids; ++gi) {
+        const BatchGrid& t = host_tab[gi];
+        mc_stats& st = stats[gi];
+        memset(&st, 0, sizeof(st));
+        st.status = t.done ? MC_OK : MC_NOT_CONVERGED;
+        ok = ok && t.done;
+        st.iters = t.iters;
+        st.cert_gap = t.checks ? t.cert : INFINITY;
+        st.energy = t.checks ? t.e[t.tau_idx] : INFINITY;
+        st.lower_bound = t.lb;
+        st.tv_gap = t.tvgap;
+        st.tau_used = taus[t.tau_idx];
+        const unsigned long long tend = t.done ? t.t_done : t_end;
+        st.ms = rate_khz > 0 ? (float)((double)(tend - t0) / (double)rate_khz) : 0.f;
+        st.checks = t.checks;
+        st.items = items;
+        if (t.checks && !isfinite(t.cert)) return set_error(MC_ERR_NUMERIC, "non-finite certificate in a batched grid");
+    }
+    MC_HIP(hipEventRecord(ev_out, s));
+    MC_HIP(hipStreamWaitEvent(us, ev_out, 0));
+    return ok ? MC_OK : MC_NOT_CONVERGED;
+}

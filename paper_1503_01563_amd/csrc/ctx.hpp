@@ -1,0 +1,52 @@
+// ctx.hpp -- the library context and error helpers shared by the C-ABI files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "launch.hpp"
+#include "mc.h"
+
+struct mc_ctx {
+    int device = 0;
+    size_t cap_n = 0;   // voxels the single-grid workspace was sized for
+    int cap_r = 0;      // families the single-grid workspace was sized for
+    float* z = nullptr;      // r*n splitting state
+    float* z2 = nullptr;     // r*n second state buffer (the sweeps never update in place)
+    float* y = nullptr;      // max(1, r-1)*n: row prox q1 (two-set) or q_j of non-final families
+    float* p = nullptr;      // r*n edge duals (check iterations)
+    float* xt = nullptr;     // n   primal estimate -w - sum_j D_j^T p_j (check iterations)
+    double* partials = nullptr;  // kReduceBlocks * kCertValues
+    double* dout = nullptr;      // kCertValues doubles
+    double* hout = nullptr;      // kCertValues doubles, pinned host
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    std::vector<hipEvent_t> prof_ev;  // MC_PROFILE: start/stop pairs of sweep launches
+
+    // batched solves
+    hipStream_t bstream = nullptr;   // capture / replay stream (default priority)
+    size_t bcap = 0;                 // floats in bbuf
+    float* bbuf = nullptr;           // per-grid state buffers, packed
+    size_t bmeta_cap = 0;            // bytes in bmeta
+    char* bmeta = nullptr;           // table, maps, partials, counters
+    std::map<unsigned long long, int> tuned_items;  // batch signature -> work items per launch
+};
+
+namespace mc {
+
+int set_error(int code, const std::string& msg);
+
+inline int hip_error(hipError_t e, const char* where)
+{
+    return set_error(MC_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace mc
+
+#define MC_HIP(call)                                         \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return mc::hip_error(e_, #call); \
+    } while (0)

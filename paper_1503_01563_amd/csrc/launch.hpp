@@ -32,7 +32,12 @@ struct PieceCfg {
     int len, pieces, overlap, tail;
 };
 
-PieceCfg piece_config(const Geo& g, int axis);
+// Pieces for a family: about `want` work items for the launch (at least 16
+// positions per piece, overlap and tail of 8 positions when cut).
+PieceCfg piece_config(const Geo& g, int axis, int want);
+constexpr int kDefaultItems = 4096;
+// dynamic LDS bytes of a sweep launch with these pieces
+size_t piece_lds_bytes(const PieceCfg& cfg);
 
 constexpr int kReduceBlocks = 512;   // blocks of the reduction kernels (fixed: deterministic)
 constexpr int kReduceThreads = 256;
@@ -78,6 +83,50 @@ hipError_t launch_cert(const Geo& g, const float* w, const float* const* a,
                        double* out, hipStream_t s);
 
 hipError_t launch_labels(const Geo& g, const float* xc, float tau, uint8_t* labels, hipStream_t s);
+
+// ---- batched two-set solves -------------------------------------------------
+
+// One 2D grid of a batch (device table entry).  Results are written on the
+// device: `done` once the certificate is below the tolerance, with the
+// iteration and a wall-clock stamp.
+struct BatchGrid {
+    Geo g;
+    const float* w;
+    const float* ax;
+    const float* ay;
+    float* z[2];     // state, ping-pong by iteration parity
+    float* q1;
+    float* p;        // 2n: row duals then column duals
+    float* xc;       // primal estimate
+    uint8_t* labels;
+    float* x_out;    // nullable
+    PieceCfg cr, cc;     // pieces of the row and column sweeps
+    int item0_r, item0_c;  // first work item of this grid in each sweep launch
+    int blk0, nblk;      // reduction blocks of this grid
+    int done, iters, checks, tau_idx;
+    double e[kNumTau], tvgap, lb, cert;
+    unsigned long long t_done;
+};
+
+struct BatchLaunch {
+    BatchGrid* tab;
+    const int* item_grid_r;  // sweep work item -> grid (rows)
+    const int* item_grid_c;  // sweep work item -> grid (columns)
+    const int* blk_grid;     // reduction block -> grid
+    int n_grids, items_r, items_c, blocks;
+    size_t lds_r, lds_c;     // dynamic LDS of the sweep launches
+};
+
+// One two-set iteration over every unfinished grid; parity selects the state
+// buffer read.  With duals, the row/column duals are written for the check.
+hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, hipStream_t s);
+// Certificate of every unfinished grid: grids whose certificate is below
+// gap_tol are marked done at iteration *iter_dev.
+hipError_t launch_batch_check(const BatchLaunch& b, float tau0, double gap_tol, const int* iter_dev,
+                              double* partials, hipStream_t s);
+hipError_t launch_batch_labels(const BatchLaunch& b, float tau0, hipStream_t s);
+hipError_t launch_set_int(int* dst, int value, hipStream_t s);
+hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
 
 hipError_t launch_energy(const Geo& g, const float* w, const float* const* a,
                          const uint8_t* labels, double* partials, double* out, hipStream_t s);

@@ -82,25 +82,31 @@ struct Ptr3 {
 // x = -w - y (the TV primal x = w - y in the paper's sign), and
 // LB(y) = sum_i min(y_i + w_i, 0).  Both are formed in FP64 from the FP32
 // duals, which stay bounded by the weights, unlike the diverging state.
+// Returns the voxel's LB term and writes its primal.
+__device__ __forceinline__ double primal_voxel(const Geo& g, const float* __restrict__ w,
+                                               const Ptr3& p, float* __restrict__ xc, int i)
+{
+    const int st[3] = {1, g.W, g.W * g.H};
+    const Coords c = coords_of(g, i);
+    const int cc[3] = {c.x, c.y, c.d};
+    double y = 0.0;
+    for (int j = 0; j < g.ndim; ++j) {
+        y -= (double)p.p[j][i];  // zero on the last slice
+        if (cc[j] > 0) y += (double)p.p[j][i - st[j]];
+    }
+    const double s = y + (double)w[i];
+    xc[i] = (float)(-s);
+    return s < 0.0 ? s : 0.0;
+}
+
 __global__ void __launch_bounds__(kReduceThreads)
 k_primal(Geo g, const float* __restrict__ w, Ptr3 p, float* __restrict__ xc,
          double* __restrict__ partials)
 {
     double lb = 0.0;
     const int stride = gridDim.x * kReduceThreads;
-    const int st[3] = {1, g.W, g.W * g.H};
-    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
-        const Coords c = coords_of(g, i);
-        const int cc[3] = {c.x, c.y, c.d};
-        double y = 0.0;
-        for (int j = 0; j < g.ndim; ++j) {
-            y -= (double)p.p[j][i];  // zero on the last slice
-            if (cc[j] > 0) y += (double)p.p[j][i - st[j]];
-        }
-        const double s = y + (double)w[i];
-        if (s < 0.0) lb += s;
-        xc[i] = (float)(-s);
-    }
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride)
+        lb += primal_voxel(g, w, p, xc, i);
     double v[1] = {lb};
     block_reduce_store<1>(v, partials + blockIdx.x);
 }
@@ -122,6 +128,36 @@ __device__ __forceinline__ int ladder_count(float x, const Taus& tz)
     return c;
 }
 
+__device__ __forceinline__ void cut_voxel(const Geo& g, const float* __restrict__ xc,
+                                          const float* __restrict__ w, const Ptr3& a,
+                                          const Ptr3& p, const Taus& tz, int i,
+                                          double (&e)[kNumTau + 1])
+{
+    const int st[3] = {1, g.W, g.W * g.H};
+    const Coords c = coords_of(g, i);
+    const int cc[3] = {c.x, c.y, c.d};
+    const int ext[3] = {g.W, g.H, g.D};
+    const float xi = xc[i];
+    const int ci = ladder_count(xi, tz);
+    const double wi = (double)w[i];
+#pragma unroll
+    for (int t = 0; t < kNumTau; ++t)
+        if (t >= ci) e[t] += wi;
+    for (int j = 0; j < g.ndim; ++j) {
+        if (cc[j] + 1 < ext[j]) {
+            const float xn = xc[i + st[j]];
+            const int cn = ladder_count(xn, tz);
+            const double aj = (double)a.p[j][i];
+            const int lo = ci < cn ? ci : cn, hi = ci < cn ? cn : ci;
+#pragma unroll
+            for (int t = 0; t < kNumTau; ++t)
+                if (t >= lo && t < hi) e[t] += aj;
+            const double dx = (double)xn - (double)xi;
+            e[kNumTau] += aj * fabs(dx) - (double)p.p[j][i] * dx;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kReduceThreads)
 k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, Ptr3 a, Ptr3 p,
              Taus tz, double* __restrict__ partials)
@@ -130,33 +166,110 @@ k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, P
 #pragma unroll
     for (int t = 0; t <= kNumTau; ++t) e[t] = 0.0;
     const int stride = gridDim.x * kReduceThreads;
-    const int st[3] = {1, g.W, g.W * g.H};
-    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
-        const Coords c = coords_of(g, i);
-        const int cc[3] = {c.x, c.y, c.d};
-        const int ext[3] = {g.W, g.H, g.D};
-        const float xi = xc[i];
-        const int ci = ladder_count(xi, tz);
-        const double wi = (double)w[i];
-#pragma unroll
-        for (int t = 0; t < kNumTau; ++t)
-            if (t >= ci) e[t] += wi;
-        for (int j = 0; j < g.ndim; ++j) {
-            if (cc[j] + 1 < ext[j]) {
-                const float xn = xc[i + st[j]];
-                const int cn = ladder_count(xn, tz);
-                const double aj = (double)a.p[j][i];
-                const int lo = ci < cn ? ci : cn, hi = ci < cn ? cn : ci;
-#pragma unroll
-                for (int t = 0; t < kNumTau; ++t)
-                    if (t >= lo && t < hi) e[t] += aj;
-                const double dx = (double)xn - (double)xi;
-                e[kNumTau] += aj * fabs(dx) - (double)p.p[j][i] * dx;
-            }
-        }
-    }
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride)
+        cut_voxel(g, xc, w, a, p, tz, i, e);
     block_reduce_store<kNumTau + 1>(e, partials + (size_t)blockIdx.x * (kNumTau + 1));
 }
+
+// ---- batched: every reduction block belongs to one grid ------------------------
+
+__device__ __forceinline__ Ptr3 batch_duals(const BatchGrid& t)
+{
+    Ptr3 p;
+    p.p[0] = t.p;
+    p.p[1] = t.p + t.g.n;
+    p.p[2] = nullptr;
+    return p;
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_batch_primal(BatchLaunch b, double* __restrict__ partials)
+{
+    const BatchGrid& t = b.tab[b.blk_grid[blockIdx.x]];
+    if (t.done) return;
+    const Ptr3 p = batch_duals(t);
+    double lb = 0.0;
+    const int stride = t.nblk * kReduceThreads;
+    for (int i = ((int)blockIdx.x - t.blk0) * kReduceThreads + threadIdx.x; i < t.g.n; i += stride)
+        lb += primal_voxel(t.g, t.w, p, t.xc, i);
+    double v[1] = {lb};
+    block_reduce_store<1>(v, partials + (size_t)blockIdx.x * kCertValues + kNumTau + 1);
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_batch_cut(BatchLaunch b, Taus tz, double* __restrict__ partials)
+{
+    const BatchGrid& t = b.tab[b.blk_grid[blockIdx.x]];
+    if (t.done) return;
+    Ptr3 a;
+    a.p[0] = t.ax;
+    a.p[1] = t.ay;
+    a.p[2] = nullptr;
+    const Ptr3 p = batch_duals(t);
+    double e[kNumTau + 1];
+#pragma unroll
+    for (int k = 0; k <= kNumTau; ++k) e[k] = 0.0;
+    const int stride = t.nblk * kReduceThreads;
+    for (int i = ((int)blockIdx.x - t.blk0) * kReduceThreads + threadIdx.x; i < t.g.n; i += stride)
+        cut_voxel(t.g, t.xc, t.w, a, p, tz, i, e);
+    block_reduce_store<kNumTau + 1>(e, partials + (size_t)blockIdx.x * kCertValues);
+}
+
+// one block per grid: fixed-order sum of the grid's block partials, then the
+// certificate and the decision
+__global__ void __launch_bounds__(kReduceThreads)
+k_batch_finalize(BatchLaunch b, const double* __restrict__ partials, double gap_tol,
+                 const int* __restrict__ iter_dev)
+{
+    BatchGrid& t = b.tab[blockIdx.x];
+    if (t.done) return;
+    double v[kCertValues];
+#pragma unroll
+    for (int q = 0; q < kCertValues; ++q) v[q] = 0.0;
+    for (int k = threadIdx.x; k < t.nblk; k += kReduceThreads) {
+#pragma unroll
+        for (int q = 0; q < kCertValues; ++q) v[q] += partials[(size_t)(t.blk0 + k) * kCertValues + q];
+    }
+    __shared__ double tot[kCertValues];
+    block_reduce_store<kCertValues>(v, tot);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double best = tot[0];
+    int bi = 0;
+    for (int q = 1; q < kNumTau; ++q) {
+        if (tot[q] < best) {
+            best = tot[q];
+            bi = q;
+        }
+    }
+    for (int q = 0; q < kNumTau; ++q) t.e[q] = tot[q];
+    t.tvgap = tot[kNumTau];
+    t.lb = tot[kNumTau + 1];
+    t.cert = best - t.lb;
+    t.tau_idx = bi;
+    t.iters = *iter_dev;
+    t.checks += 1;
+    if (t.cert < gap_tol) {
+        t.done = 1;
+        t.t_done = wall_clock64();
+    }
+}
+
+__global__ void __launch_bounds__(kReduceThreads) k_batch_labels(BatchLaunch b, Taus tz)
+{
+    const BatchGrid& t = b.tab[b.blk_grid[blockIdx.x]];
+    const float tau = tz.t[t.tau_idx];
+    const int stride = t.nblk * kReduceThreads;
+    for (int i = ((int)blockIdx.x - t.blk0) * kReduceThreads + threadIdx.x; i < t.g.n; i += stride) {
+        const float x = t.xc[i];
+        t.labels[i] = x > tau ? 1 : 0;
+        if (t.x_out) t.x_out[i] = x;
+    }
+}
+
+__global__ void k_set_int(int* dst, int v) { *dst = v; }
+
+__global__ void k_stamp(unsigned long long* dst) { *dst = wall_clock64(); }
 
 __global__ void __launch_bounds__(kReduceThreads)
 k_energy(Geo g, const float* __restrict__ w, Ptr3 a, const uint8_t* __restrict__ lab,
@@ -251,6 +364,38 @@ hipError_t launch_cert(const Geo& g, const float* w, const float* const* a,
                        out);
     hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, part_lb, nb,
                        out + kNumTau + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_check(const BatchLaunch& b, float tau0, double gap_tol, const int* iter_dev,
+                              double* partials, hipStream_t s)
+{
+    Taus tz;
+    tau_ladder(tau0, tz.t);
+    hipLaunchKernelGGL(k_batch_primal, dim3(b.blocks), dim3(kReduceThreads), 0, s, b, partials);
+    hipLaunchKernelGGL(k_batch_cut, dim3(b.blocks), dim3(kReduceThreads), 0, s, b, tz, partials);
+    hipLaunchKernelGGL(k_batch_finalize, dim3(b.n_grids), dim3(kReduceThreads), 0, s, b, partials,
+                       gap_tol, iter_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_labels(const BatchLaunch& b, float tau0, hipStream_t s)
+{
+    Taus tz;
+    tau_ladder(tau0, tz.t);
+    hipLaunchKernelGGL(k_batch_labels, dim3(b.blocks), dim3(kReduceThreads), 0, s, b, tz);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* dst, int value, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, s, dst, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(unsigned long long* dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(1), 0, s, dst);
     return hipGetLastError();
 }
 

@@ -382,19 +382,58 @@ hipError_t launch_mode_x(const Geo& g, int axis, const M& mode, const PieceCfg& 
 template <class M>
 hipError_t launch_mode(const Geo& g, int axis, const M& mode, bool duals, hipStream_t s)
 {
-    const PieceCfg cfg = piece_config(g, axis);
+    const PieceCfg cfg = piece_config(g, axis, kDefaultItems);
     return duals ? launch_mode_x<M, true>(g, axis, mode, cfg, s)
                  : launch_mode_x<M, false>(g, axis, mode, cfg, s);
 }
 
+// ---- batched two-set iteration ----------------------------------------------------
+
+template <bool kExact>
+__global__ void __launch_bounds__(kLanes) k_batch_rows(BatchLaunch b, int parity)
+{
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    const int gi = b.item_grid_r[blockIdx.x];
+    const BatchGrid& t = b.tab[gi];
+    if (t.done) return;
+    ModeRows2 m{t.z[parity], t.ax, t.q1, kExact ? t.p : nullptr};
+    sweep_piece<ModeRows2, true, kExact>(t.g, 0, (int)blockIdx.x - t.item0_r, m, t.cr, lds);
+}
+
+template <bool kExact>
+__global__ void __launch_bounds__(kLanes) k_batch_cols(BatchLaunch b, int parity)
+{
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    const int gi = b.item_grid_c[blockIdx.x];
+    const BatchGrid& t = b.tab[gi];
+    if (t.done) return;
+    ModeCols2 m{t.q1, t.z[parity], t.z[parity ^ 1], t.w, t.ay, kExact ? t.p + t.g.n : nullptr};
+    sweep_piece<ModeCols2, false, kExact>(t.g, 1, (int)blockIdx.x - t.item0_c, m, t.cc, lds);
+}
+
 }  // namespace
 
-PieceCfg piece_config(const Geo& g, int axis)
+hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, hipStream_t s)
 {
-    // enough work items to give every SIMD a few waves, pieces of at least 16
+    if (duals) {
+        hipLaunchKernelGGL(k_batch_rows<true>, dim3(b.items_r), dim3(kLanes), b.lds_r, s, b, parity);
+        hipLaunchKernelGGL(k_batch_cols<true>, dim3(b.items_c), dim3(kLanes), b.lds_c, s, b, parity);
+    } else {
+        hipLaunchKernelGGL(k_batch_rows<false>, dim3(b.items_r), dim3(kLanes), b.lds_r, s, b, parity);
+        hipLaunchKernelGGL(k_batch_cols<false>, dim3(b.items_c), dim3(kLanes), b.lds_c, s, b, parity);
+    }
+    return hipGetLastError();
+}
+
+size_t piece_lds_bytes(const PieceCfg& cfg) { return lds_bytes(cfg); }
+
+
+PieceCfg piece_config(const Geo& g, int axis, int want)
+{
+    // about `want` work items, pieces of at least 16 positions
     const int m = geo_extent(g, axis);
     const int groups = (geo_nchains(g, axis) + kLanes - 1) / kLanes;
-    const int want = 4096;
+    if (want < 1) want = 1;
     int pieces = (want + groups - 1) / groups;
     int len = (m + pieces - 1) / pieces;
     len = len < 16 ? 16 : ((len + 15) / 16) * 16;
@@ -435,7 +474,7 @@ hipError_t launch_drp_sweeps(const Geo& g, int nfam, const float* z, const float
     if (nfam == 1) return launch_mode(g, 0, m0, p != nullptr, s);
     if (nfam != 2) return hipErrorInvalidValue;
     ModeSweepP m1{z + n, a[1], q + n, p ? p + n : nullptr};
-    const PieceCfg c0 = piece_config(g, 0), c1 = piece_config(g, 1);
+    const PieceCfg c0 = piece_config(g, 0, kDefaultItems), c1 = piece_config(g, 1, kDefaultItems);
     const int n0 = items_of(g, 0, c0), n1 = items_of(g, 1, c1);
     const size_t shm = lds_bytes(c0) > lds_bytes(c1) ? lds_bytes(c0) : lds_bytes(c1);
     if (p)

@@ -53,7 +53,7 @@ class Stats(ctypes.Structure):
                 ("lower_bound", ctypes.c_double), ("tv_gap", ctypes.c_double),
                 ("tau_used", ctypes.c_float), ("ms", ctypes.c_float),
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
-                ("checks", ctypes.c_int32)]
+                ("checks", ctypes.c_int32), ("items", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
 
 
 _lib = None
@@ -83,6 +83,9 @@ def load_library():
         lib.mc_tv_prox_chains.restype = ctypes.c_int
         lib.mc_cut_energy.argtypes = [P, ctypes.POINTER(Grid), P, P, P, ctypes.POINTER(ctypes.c_double), P]
         lib.mc_cut_energy.restype = ctypes.c_int
+        lib.mc_tv_solve_batched.argtypes = [P, ctypes.c_int, ctypes.POINTER(Grid), P, P, P, P,
+                                            ctypes.POINTER(Stats), ctypes.POINTER(Opts), P]
+        lib.mc_tv_solve_batched.restype = ctypes.c_int
         lib.mc_status_string.argtypes = [ctypes.c_int]
         lib.mc_status_string.restype = ctypes.c_char_p
         lib.mc_last_error.argtypes = []
@@ -250,3 +253,65 @@ def cut_energy(w: torch.Tensor, a: Sequence[torch.Tensor], labels: torch.Tensor)
                            ctypes.byref(e), _stream(dev))
     _check(rc)
     return e.value
+
+
+@dataclass
+class BatchResult:
+    labels: list
+    x: Optional[list]
+    status: list
+    iters: list
+    cert_gap: list
+    energy: list
+    ms: list
+    items: int
+
+    @property
+    def converged(self):
+        return all(s == MC_OK for s in self.status)
+
+
+def tv_solve_batched(ws: Sequence[torch.Tensor], As: Sequence[Sequence[torch.Tensor]], max_iters=500,
+                     check_every=2, gap_tol=1e-3, tau0=1e-3, items=0, return_x=False) -> BatchResult:
+    """Minimum cuts of several 2D grids at once (mc_tv_solve_batched).
+
+    ws[g] is the (H_g, W_g) unary tensor of grid g, As[g] = (a_x, a_y).
+    items > 0 fixes the work items per sweep launch (0: tuned on first use).
+    """
+    lib = load_library()
+    ng = len(ws)
+    if ng < 1 or len(As) != ng:
+        raise ValueError("need one weight pair per grid")
+    dev = ws[0].device.index if ws[0].device.index is not None else torch.cuda.current_device()
+    grids = (Grid * ng)()
+    wp = (ctypes.c_void_p * ng)()
+    ap = (ctypes.c_void_p * (2 * ng))()
+    lp = (ctypes.c_void_p * ng)()
+    xp = (ctypes.c_void_p * ng)()
+    labels, xs = [], []
+    for g in range(ng):
+        shape = tuple(ws[g].shape)
+        if len(shape) != 2:
+            raise ValueError("batched grids must be 2D")
+        grids[g] = _grid(shape)
+        wp[g] = _dev_f32(ws[g], shape, "w[%d]" % g).value
+        ap[2 * g] = _dev_f32(As[g][0], shape, "a_x[%d]" % g).value
+        ap[2 * g + 1] = _dev_f32(As[g][1], shape, "a_y[%d]" % g).value
+        lab = torch.empty(shape, dtype=torch.uint8, device=ws[g].device)
+        labels.append(lab)
+        lp[g] = lab.data_ptr()
+        if return_x:
+            x = torch.empty(shape, dtype=torch.float32, device=ws[g].device)
+            xs.append(x)
+            xp[g] = x.data_ptr()
+    st = (Stats * ng)()
+    o = make_opts(max_iters, check_every, gap_tol, VARIANT_AUTO, tau0)
+    o.reserved[0] = int(items)
+    rc = lib.mc_tv_solve_batched(context(dev), ng, grids, ctypes.cast(wp, ctypes.c_void_p),
+                                 ctypes.cast(ap, ctypes.c_void_p), ctypes.cast(lp, ctypes.c_void_p),
+                                 ctypes.cast(xp, ctypes.c_void_p) if return_x else None,
+                                 st, ctypes.byref(o), _stream(dev))
+    _check(rc, allow_not_converged=True)
+    return BatchResult(labels, xs if return_x else None, [s.status for s in st],
+                       [s.iters for s in st], [s.cert_gap for s in st], [s.energy for s in st],
+                       [s.ms for s in st], st[0].items)

@@ -30,7 +30,7 @@ def libpath():
 
 def test_header_declares_boundary():
     names = declared_functions()
-    for n in ("mc_tv_solve", "mc_tv_prox_chains", "mc_cut_energy", "mc_ctx_create",
+    for n in ("mc_tv_solve", "mc_tv_prox_chains", "mc_cut_energy", "mc_tv_solve_batched", "mc_ctx_create",
               "mc_ctx_destroy", "mc_status_string", "mc_last_error", "mc_opts_default"):
         assert n in names
 
@@ -65,5 +65,5 @@ def test_struct_layouts_match_header():
     from paper_1503_01563_amd import mc
     assert ctypes.sizeof(mc.Grid) == 32
     assert ctypes.sizeof(mc.Opts) == 48
-    assert ctypes.sizeof(mc.Stats) == 64
+    assert ctypes.sizeof(mc.Stats) == 72
     assert mc.Stats.ms.offset == 44 and mc.Opts.flags.offset == 24
