@@ -129,3 +129,20 @@ def config_batch(seed=4000, count=64):
 def config_warm(seed, shape=(512, 512)):
     """512x512 integer grid for the learned warm start."""
     return iid_grid(shape, seed)
+
+
+# Warm-start network ---------------------------------------------------------
+
+NET_LAYERS = ((3, 32), (32, 32), (32, 32), (32, 2))
+
+
+def net_init(seed):
+    """Seeded He-normal initial parameters of the 4-layer 3x3 network, biases 0.
+
+    Flat float32 vector: for each layer W (index order co, ky, kx, ci), then b."""
+    rng = _rng(seed)
+    parts = []
+    for ci, co in NET_LAYERS:
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / (9 * ci)), size=co * 9 * ci))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
