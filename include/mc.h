@@ -171,6 +171,51 @@ int mc_tv_solve_batched(mc_ctx *ctx, int n_grids, const mc_grid *grids,
                         uint8_t *const *labels, float *const *x_out, mc_stats *stats,
                         const mc_opts *opts, void *stream);
 
+/*
+ * Learned warm start (2D, two-set form).  The paper starts DR from earlier
+ * dual vectors when problems are related (Sec. 4.4, 6.1); here a small
+ * convolutional network proposes the starting state instead:
+ *   features (w/20, a_x/10, a_y/10) -> three conv3x3 + ReLU layers of 32
+ *   channels -> conv3x3 -> two channels: x0 (a guess of the TV solution) and
+ *   p1 (a guess of the row-family edge duals).
+ * conv3x3 is the zero-padded cross-correlation
+ *   out[y,x,co] = b[co] + sum_{ky,kx,ci} W[co,ky,kx,ci] in[y+ky-1, x+kx-1, ci].
+ * Weights and activations are BF16 on the device, sums FP32 (MFMA).
+ * Parameters: one FP32 device vector of mc_ws_param_count() entries; for each
+ * layer (cin, cout) in (3,32), (32,32), (32,32), (32,2): W in index order
+ * (co, ky, kx, ci), then b.
+ * Images: w, a_x, a_y are [batch][H][W] FP32 device arrays (a_x weights along
+ * W, a_y along H, as in mc_tv_solve); out and target are [batch][2][H][W]
+ * (plane 0 x0, plane 1 p1).  The network's scratch lives in the context.
+ */
+int mc_ws_param_count(void);
+
+/* Network output for a batch of images (asynchronous on `stream`). */
+int mc_ws_forward(mc_ctx *ctx, const float *params, int batch, int H, int W,
+                  const float *w, const float *a_x, const float *a_y, float *out,
+                  void *stream);
+
+/* Forward pass, mean-squared-error loss against `target` (mean over all
+ * batch*2*H*W outputs) and its gradient: grad [mc_ws_param_count()] is
+ * overwritten.  loss (host, nullable) receives the FP64 loss; giving it
+ * synchronises the stream. */
+int mc_ws_backward(mc_ctx *ctx, const float *params, int batch, int H, int W,
+                   const float *w, const float *a_x, const float *a_y,
+                   const float *target, float *grad, double *loss, void *stream);
+
+/* One Adam step (step counts from 1, bias-corrected) on the FP32 master
+ * parameters, in place; m and v are the moment vectors (zero before step 1). */
+int mc_ws_adam_step(mc_ctx *ctx, float *params, const float *grad, float *m, float *v,
+                    int step, float lr, float beta1, float beta2, float eps,
+                    void *stream);
+
+/* Starting state of the two-set splitting from one network output
+ * out [2][H][W]: z0 = c x0 + D_rows^T clip(p1, -a_x, a_x), where
+ * (D^T p)[y][x] = p[y][x-1] - p[y][x] (0 outside the row).  The dual part lies
+ * in the row family's set K exactly.  z0 [H*W] is passed to mc_tv_solve. */
+int mc_ws_warm_state(mc_ctx *ctx, const mc_grid *grid, const float *out,
+                     const float *a_x, float c, float *z0, void *stream);
+
 /* Text for a status code, and the calling thread's last error message. */
 const char *mc_status_string(int code);
 const char *mc_last_error(void);

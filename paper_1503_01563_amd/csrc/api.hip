@@ -206,6 +206,7 @@ int mc_ctx_destroy(mc_ctx* c)
     for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
     hipFree(c->bbuf);
     hipFree(c->bmeta);
+    hipFree(c->nbuf);
     if (c->bstream) hipStreamDestroy(c->bstream);
     delete c;
     return MC_OK;

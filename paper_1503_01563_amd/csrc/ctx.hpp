@@ -32,6 +32,10 @@ struct mc_ctx {
     size_t bmeta_cap = 0;            // bytes in bmeta
     char* bmeta = nullptr;           // table, maps, partials, counters
     std::map<unsigned long long, int> tuned_items;  // batch signature -> work items per launch
+
+    // warm-start network
+    size_t ncap = 0;        // bytes in nbuf
+    char* nbuf = nullptr;   // packed weights, activations, gradients, partials
 };
 
 namespace mc {

@@ -86,6 +86,17 @@ def load_library():
         lib.mc_tv_solve_batched.argtypes = [P, ctypes.c_int, ctypes.POINTER(Grid), P, P, P, P,
                                             ctypes.POINTER(Stats), ctypes.POINTER(Opts), P]
         lib.mc_tv_solve_batched.restype = ctypes.c_int
+        lib.mc_ws_param_count.argtypes = []
+        lib.mc_ws_param_count.restype = ctypes.c_int
+        I, F = ctypes.c_int, ctypes.c_float
+        lib.mc_ws_forward.argtypes = [P, P, I, I, I, P, P, P, P, P]
+        lib.mc_ws_forward.restype = ctypes.c_int
+        lib.mc_ws_backward.argtypes = [P, P, I, I, I, P, P, P, P, P, ctypes.POINTER(ctypes.c_double), P]
+        lib.mc_ws_backward.restype = ctypes.c_int
+        lib.mc_ws_adam_step.argtypes = [P, P, P, P, P, I, F, F, F, F, P]
+        lib.mc_ws_adam_step.restype = ctypes.c_int
+        lib.mc_ws_warm_state.argtypes = [P, ctypes.POINTER(Grid), P, P, F, P, P]
+        lib.mc_ws_warm_state.restype = ctypes.c_int
         lib.mc_status_string.argtypes = [ctypes.c_int]
         lib.mc_status_string.restype = ctypes.c_char_p
         lib.mc_last_error.argtypes = []
@@ -315,3 +326,78 @@ def tv_solve_batched(ws: Sequence[torch.Tensor], As: Sequence[Sequence[torch.Ten
     return BatchResult(labels, xs if return_x else None, [s.status for s in st],
                        [s.iters for s in st], [s.cert_gap for s in st], [s.energy for s in st],
                        [s.ms for s in st], st[0].items)
+
+
+# ---- learned warm start ------------------------------------------------------------
+
+def ws_param_count() -> int:
+    return int(load_library().mc_ws_param_count())
+
+
+def _images(w, a_x, a_y):
+    """Accept (H, W) or (B, H, W) tensors; returns the batch shape and pointers."""
+    if w.dim() == 2:
+        w, a_x, a_y = w.unsqueeze(0), a_x.unsqueeze(0), a_y.unsqueeze(0)
+    if w.dim() != 3:
+        raise ValueError("images must be (H, W) or (B, H, W)")
+    shape = tuple(w.shape)
+    return shape, (_dev_f32(w, shape, "w"), _dev_f32(a_x, shape, "a_x"), _dev_f32(a_y, shape, "a_y"))
+
+
+def _params(params):
+    return _dev_f32(params, (ws_param_count(),), "params")
+
+
+def ws_forward(params: torch.Tensor, w: torch.Tensor, a_x: torch.Tensor, a_y: torch.Tensor,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Network output (B, 2, H, W) for images (B, H, W) or (H, W) (mc_ws_forward)."""
+    lib = load_library()
+    (B, H, W), ptrs = _images(w, a_x, a_y)
+    dev = w.device.index if w.device.index is not None else torch.cuda.current_device()
+    o = out if out is not None else torch.empty((B, 2, H, W), dtype=torch.float32, device=w.device)
+    op = _dev_f32(o, (B, 2, H, W), "out")
+    _check(lib.mc_ws_forward(context(dev), _params(params), B, H, W, *ptrs, op, _stream(dev)))
+    return o
+
+
+def ws_backward(params, w, a_x, a_y, target, grad: Optional[torch.Tensor] = None, want_loss=True):
+    """(grad, loss) of the mean-squared error against target (B, 2, H, W)."""
+    lib = load_library()
+    (B, H, W), ptrs = _images(w, a_x, a_y)
+    dev = w.device.index if w.device.index is not None else torch.cuda.current_device()
+    if target.dim() == 3:
+        target = target.unsqueeze(0)
+    tp = _dev_f32(target, (B, 2, H, W), "target")
+    g = grad if grad is not None else torch.empty(ws_param_count(), dtype=torch.float32, device=w.device)
+    gp = _dev_f32(g, (ws_param_count(),), "grad")
+    loss = ctypes.c_double(float("nan"))
+    _check(lib.mc_ws_backward(context(dev), _params(params), B, H, W, *ptrs, tp, gp,
+                              ctypes.byref(loss) if want_loss else None, _stream(dev)))
+    return g, (loss.value if want_loss else None)
+
+
+def ws_adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of params, m, v (mc_ws_adam_step)."""
+    lib = load_library()
+    n = ws_param_count()
+    dev = params.device.index if params.device.index is not None else torch.cuda.current_device()
+    ptrs = [_dev_f32(t, (n,), name) for t, name in ((params, "params"), (grad, "grad"), (m, "m"), (v, "v"))]
+    _check(lib.mc_ws_adam_step(context(dev), *ptrs, int(step), float(lr), float(beta1), float(beta2),
+                               float(eps), _stream(dev)))
+
+
+def ws_warm_state(out: torch.Tensor, a_x: torch.Tensor, c: float = 0.0) -> torch.Tensor:
+    """Starting state z0 (H, W) of the two-set splitting from out (2, H, W)."""
+    lib = load_library()
+    if out.dim() == 4:
+        if out.shape[0] != 1:
+            raise ValueError("one image at a time")
+        out = out[0]
+    H, W = int(out.shape[1]), int(out.shape[2])
+    dev = out.device.index if out.device.index is not None else torch.cuda.current_device()
+    op = _dev_f32(out, (2, H, W), "out")
+    ap = _dev_f32(a_x, (H, W), "a_x")
+    z0 = torch.empty((H, W), dtype=torch.float32, device=out.device)
+    _check(lib.mc_ws_warm_state(context(dev), ctypes.byref(_grid((H, W))), op, ap, float(c),
+                                ctypes.c_void_p(z0.data_ptr()), _stream(dev)))
+    return z0

@@ -31,7 +31,8 @@ def libpath():
 def test_header_declares_boundary():
     names = declared_functions()
     for n in ("mc_tv_solve", "mc_tv_prox_chains", "mc_cut_energy", "mc_tv_solve_batched", "mc_ctx_create",
-              "mc_ctx_destroy", "mc_status_string", "mc_last_error", "mc_opts_default"):
+              "mc_ctx_destroy", "mc_status_string", "mc_last_error", "mc_opts_default", "mc_ws_param_count",
+              "mc_ws_forward", "mc_ws_backward", "mc_ws_adam_step", "mc_ws_warm_state"):
         assert n in names
 
 
@@ -59,6 +60,12 @@ def test_host_only_calls(libpath):
     assert lib.mc_tv_prox_chains(None, None, 0, None, None, None, None, None) == -1
     assert b"ctx" in lib.mc_last_error()
     assert lib.mc_ctx_destroy(None) == 0
+    # warm-start network: parameter count agrees with the reference layout
+    from oracle import convnet
+    assert mc.ws_param_count() == convnet.param_count() == 19970
+    assert lib.mc_ws_forward(None, None, 1, 1, 1, None, None, None, None, None) == -1
+    assert lib.mc_ws_adam_step(None, None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, None) == -1
+    assert lib.mc_ws_warm_state(None, None, None, None, 0.0, None, None) == -1
 
 
 def test_struct_layouts_match_header():
