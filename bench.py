@@ -10,9 +10,11 @@ Prints one JSON line.  `value` is voxel-sweeps per second over the timed
 steps (voxels x chain families x iterations / wall time).  `roofline` rates the
 chain-sweep kernels (the dominant kernels) by their event-timed launches
 against HBM bandwidth, with 16 algorithmic bytes per voxel-sweep.
-`cpu_baseline` times the CPU oracle (FP64, one thread) on a bounded number of
-iterations of the same problem, and checks the GPU cut against the oracle's
-max-flow energy.
+`warm_start` compares the time to the exact cut from a cold start and from
+the trained network's warm start on held-out 512x512 grids (outside the timed
+steps).  `cpu_baseline` times the CPU oracle (FP64, one thread) on a bounded
+number of iterations of the same problem, and checks the GPU cut against the
+oracle's max-flow energy.
 """
 import argparse
 import json
@@ -40,6 +42,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="approximate CPU time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm-grids", type=int, default=16,
+                    help="held-out 512x512 grids for the cold vs warm-start comparison (0: skip)")
     return ap.parse_args()
 
 
@@ -142,14 +146,42 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "k_dr2_rows + k_dr2_cols (chain-prox sweeps)",
+            "kernel": "k_sweep<ModeRows2> + k_sweep<ModeCols2> (chain-prox sweeps)",
             "avg_launch_us": 1e6 * avg_launch_s,
             "bytes_per_launch": bytes_per_launch,
         },
     }
+    if args.warm_grids > 0:
+        out["warm_start"] = warm_start_section(args.warm_grids)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a, last.energy, args.cpu_seconds)
     print(json.dumps(out))
+
+
+def warm_start_section(n_grids):
+    """Time to exact cut, cold vs learned warm start, on held-out 512x512 grids."""
+    import numpy as np
+
+    from paper_1503_01563_amd import warmstart
+    params, c = warmstart.load_params()
+    seeds = range(warmstart.TEST_SEED0, warmstart.TEST_SEED0 + n_grids)
+    rows = warmstart.compare(params, c, seeds, repeats=3)
+    cold_ms = [r["cold_ms"] for r in rows]
+    warm_ms = [r["warm_ms"] for r in rows]
+    return {
+        "workload": "%d held-out 512x512 integer grids (w in [-20,20], a in [0,10]), seeds %d.."
+                    % (n_grids, warmstart.TEST_SEED0),
+        "c": c,
+        "cold_ms_median": float(np.median(cold_ms)),
+        "warm_ms_median": float(np.median(warm_ms)),
+        "cold_ms_total": float(np.sum(cold_ms)),
+        "warm_ms_total": float(np.sum(warm_ms)),
+        "cold_iters_total": int(sum(r["cold_iters"] for r in rows)),
+        "warm_iters_total": int(sum(r["warm_iters"] for r in rows)),
+        "all_certified": all(r["cold_ok"] and r["warm_ok"] for r in rows),
+        "same_energy": all(r["cold_energy"] == r["warm_energy"] for r in rows),
+        "note": "warm time includes network inference and the warm state",
+    }
 
 
 if __name__ == "__main__":

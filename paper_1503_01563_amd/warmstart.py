@@ -1,0 +1,206 @@
+"""Learned warm start: data, training and use of the warm-start network.
+
+Every numerical step runs in libmc (mc_tv_solve for the training targets,
+mc_ws_backward / mc_ws_adam_step for training, mc_ws_forward and
+mc_ws_warm_state for inference); this module only orchestrates them.
+
+Targets.  For a grid (w, a) the two-set splitting converges to a state
+z = y1* + k x* (Sec. 4.3: with an optimal primal x* the reflections move z
+along x* while the row-family dual y1* stays fixed).  The network learns x*
+and the row edge duals p1* with y1* = D_rows^T p1*; p1* are the duals of the
+row prox of the final state.  The starting state built from a prediction is
+z0 = c x0 + D_rows^T clip(p1, -a_x, a_x).
+
+Command line (runs on a GPU):
+  python -m paper_1503_01563_amd.warmstart train --out DIR [--n-train N ...]
+writes DIR/warm_start_params.npy and DIR/warm_start.json.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import gen, mc
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+PARAMS_FILE = os.path.join(_PKG, "warm_start_params.npy")
+META_FILE = os.path.join(_PKG, "warm_start.json")
+
+TRAIN_SEED0, VAL_SEED0, TEST_SEED0 = 100000, 120000, 130000
+
+
+def _t(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+
+
+def solver_targets(w, a, iters):
+    """(x*, p1*) of one 2D grid from `iters` plain iterations (device tensors)."""
+    r = mc.tv_solve(w, a, max_iters=iters, check_every=iters, gap_tol=0.0, return_x=True, return_z=True)
+    _, p1 = mc.tv_prox_chains(r.z.view(w.shape), a[0], 0, return_p=True)
+    return r.x, p1
+
+
+@dataclass
+class Dataset:
+    inputs: torch.Tensor   # (N, 3, H, W): w, a_x, a_y
+    targets: torch.Tensor  # (N, 2, H, W): x*, p1*
+
+
+def build_dataset(seeds, shape=(512, 512), iters=400, dev=None, log=print):
+    dev = dev or torch.device("cuda:0")
+    n = len(seeds)
+    inputs = torch.empty((n, 3) + tuple(shape), dtype=torch.float32, device=dev)
+    targets = torch.empty((n, 2) + tuple(shape), dtype=torch.float32, device=dev)
+    t0 = time.time()
+    for i, s in enumerate(seeds):
+        w, a = gen.config_warm(s, shape)
+        inputs[i, 0].copy_(_t(w, dev))
+        inputs[i, 1].copy_(_t(a[0], dev))
+        inputs[i, 2].copy_(_t(a[1], dev))
+        x, p1 = solver_targets(inputs[i, 0], [inputs[i, 1], inputs[i, 2]], iters)
+        targets[i, 0].copy_(x)
+        targets[i, 1].copy_(p1)
+        if (i + 1) % 200 == 0 or i + 1 == n:
+            log("targets %d/%d (%.1f s)" % (i + 1, n, time.time() - t0))
+    return Dataset(inputs, targets)
+
+
+def train(data: Dataset, steps=3000, batch=16, crop=128, lr=2e-3, lr_end=1e-4, seed=0, log=print):
+    """Adam on random crops; returns the FP32 parameter tensor and the loss history."""
+    dev = data.inputs.device
+    n, _, H, W = data.inputs.shape
+    gen_ = torch.Generator(device="cpu").manual_seed(seed)
+    params = _t(gen.net_init(seed), dev)
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    grad = torch.empty_like(params)
+    xb = torch.empty((3, batch, crop, crop), dtype=torch.float32, device=dev)
+    tb = torch.empty((batch, 2, crop, crop), dtype=torch.float32, device=dev)
+    hist = []
+    t0 = time.time()
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, n, (batch,), generator=gen_)
+        oy = torch.randint(0, H - crop + 1, (batch,), generator=gen_)
+        ox = torch.randint(0, W - crop + 1, (batch,), generator=gen_)
+        for b in range(batch):
+            i, y, x = int(idx[b]), int(oy[b]), int(ox[b])
+            xb[:, b].copy_(data.inputs[i, :, y:y + crop, x:x + crop])
+            tb[b].copy_(data.targets[i, :, y:y + crop, x:x + crop])
+        want = step % 100 == 0 or step == 1
+        _, loss = mc.ws_backward(params, xb[0], xb[1], xb[2], tb, grad=grad, want_loss=want)
+        frac = (step - 1) / max(1, steps - 1)
+        lr_t = lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * frac))
+        mc.ws_adam_step(params, grad, m, v, step, lr_t)
+        if want:
+            hist.append((step, loss))
+            if step % 500 == 0 or step == 1:
+                log("step %d loss %.4f lr %.2e (%.1f s)" % (step, loss, lr_t, time.time() - t0))
+    return params, hist
+
+
+def warm_state(params, w, a_x, a_y, c):
+    out = mc.ws_forward(params, w, a_x, a_y)
+    return mc.ws_warm_state(out[0], a_x, c)
+
+
+@dataclass
+class TimedSolve:
+    result: mc.SolveResult
+    ms: float  # device time from the first kernel to the certified cut, network included
+
+
+def timed_solve(w, a, params=None, c=0.0, max_iters=3000, check_every=2, gap_tol=1e-3):
+    """Cold (params None) or warm solve, timed with events on the current stream."""
+    s = torch.cuda.current_stream(w.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    z0 = warm_state(params, w, a[0], a[1], c) if params is not None else None
+    r = mc.tv_solve(w, a, z0=z0, max_iters=max_iters, check_every=check_every, gap_tol=gap_tol,
+                    return_x=False)
+    e1.record(s)
+    e1.synchronize()
+    return TimedSolve(r, e0.elapsed_time(e1))
+
+
+def compare(params, c, seeds, shape=(512, 512), check_every=2, dev=None, repeats=1):
+    """Per grid: cold and warm iterations, times (ms) and energies."""
+    dev = dev or torch.device("cuda:0")
+    rows = []
+    for s in seeds:
+        w, a = gen.config_warm(s, shape)
+        tw, ta = _t(w, dev), [_t(a[0], dev), _t(a[1], dev)]
+        cold = [timed_solve(tw, ta, None, check_every=check_every) for _ in range(repeats)]
+        warm = [timed_solve(tw, ta, params, c, check_every=check_every) for _ in range(repeats)]
+        rows.append({"seed": s, "cold_iters": cold[-1].result.iters, "warm_iters": warm[-1].result.iters,
+                     "cold_ms": float(np.median([t.ms for t in cold])),
+                     "warm_ms": float(np.median([t.ms for t in warm])),
+                     "cold_energy": cold[-1].result.energy, "warm_energy": warm[-1].result.energy,
+                     "cold_ok": cold[-1].result.converged, "warm_ok": warm[-1].result.converged})
+    return rows
+
+
+def load_params(dev=None):
+    """Trained parameters and warm coefficient c shipped with the package."""
+    dev = dev or torch.device("cuda:0")
+    p = np.load(PARAMS_FILE, allow_pickle=False)
+    meta = json.load(open(META_FILE))
+    return _t(p, dev), float(meta["c"])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train"])
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--n-train", type=int, default=2000)
+    ap.add_argument("--target-iters", type=int, default=400)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--crop", type=int, default=128)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--n-val", type=int, default=16)
+    ap.add_argument("--n-test", type=int, default=16)
+    args = ap.parse_args()
+    os.makedirs(args.out, exist_ok=True)
+    log = lambda m: print(m, flush=True)
+    dev = torch.device("cuda:0")
+    data = build_dataset(range(TRAIN_SEED0, TRAIN_SEED0 + args.n_train), iters=args.target_iters, log=log)
+    params, hist = train(data, steps=args.steps, batch=args.batch, crop=args.crop, lr=args.lr, log=log)
+    del data
+    torch.cuda.empty_cache()
+    best = None
+    for c in (0.0, 0.5, 1.0):
+        rows = compare(params, c, range(VAL_SEED0, VAL_SEED0 + args.n_val), dev=dev)
+        ci = sum(r["cold_iters"] for r in rows)
+        wi = sum(r["warm_iters"] for r in rows)
+        log("validation c=%.1f: cold iters %d, warm iters %d" % (c, ci, wi))
+        if best is None or wi < best[1]:
+            best = (c, wi, ci)
+    c = best[0]
+    rows = compare(params, c, range(TEST_SEED0, TEST_SEED0 + args.n_test), dev=dev, repeats=3)
+    summary = {
+        "c": c, "n_train": args.n_train, "target_iters": args.target_iters, "steps": args.steps,
+        "batch": args.batch, "crop": args.crop, "lr": args.lr, "final_loss": hist[-1][1],
+        "loss_history": hist[::5],
+        "validation": {"c": c, "warm_iters": best[1], "cold_iters": best[2]},
+        "test": rows,
+        "test_cold_iters": sum(r["cold_iters"] for r in rows),
+        "test_warm_iters": sum(r["warm_iters"] for r in rows),
+        "test_cold_ms_median": float(np.median([r["cold_ms"] for r in rows])),
+        "test_warm_ms_median": float(np.median([r["warm_ms"] for r in rows])),
+    }
+    np.save(os.path.join(args.out, "warm_start_params.npy"), params.cpu().numpy())
+    with open(os.path.join(args.out, "warm_start.json"), "w") as f:
+        json.dump(summary, f, indent=1)
+    log("test: cold iters %d warm iters %d; median ms cold %.2f warm %.2f" % (
+        summary["test_cold_iters"], summary["test_warm_iters"], summary["test_cold_ms_median"],
+        summary["test_warm_ms_median"]))
+
+
+if __name__ == "__main__":
+    main()

@@ -161,3 +161,29 @@ def test_training_reduces_loss(dev):
     _, l1 = mc.ws_backward(p, tw, tax, tay, target, grad=g)
     print("training loss %.4f -> %.4f" % (l0, l1))
     assert np.isfinite(l1) and l1 < 0.5 * l0
+
+
+def test_trained_warm_start_gain(dev):
+    """The shipped trained network on 16 held-out 512x512 integer grids: cold and
+    warm starts both reach the exact minimum cut (energy equal to max-flow),
+    and the warm start needs fewer iterations in total."""
+    import oracle
+    from paper_1503_01563_amd import warmstart
+    params, c = warmstart.load_params(dev)
+    cold_it = warm_it = 0
+    cold_ms, warm_ms = [], []
+    for s in range(warmstart.TEST_SEED0, warmstart.TEST_SEED0 + 16):
+        w, a = gen.config_warm(s)
+        e_star = oracle.mincut(w, a, "dinic")[0]
+        tw, ta = T(w, dev), [T(a[0], dev), T(a[1], dev)]
+        cold = warmstart.timed_solve(tw, ta)
+        warm = warmstart.timed_solve(tw, ta, params, c)
+        assert cold.result.converged and warm.result.converged, s
+        assert cold.result.energy == e_star and warm.result.energy == e_star, s
+        cold_it += cold.result.iters
+        warm_it += warm.result.iters
+        cold_ms.append(cold.ms)
+        warm_ms.append(warm.ms)
+    print("iterations cold %d warm %d; median ms cold %.2f warm %.2f"
+          % (cold_it, warm_it, np.median(cold_ms), np.median(warm_ms)))
+    assert warm_it < cold_it
