@@ -15,6 +15,7 @@
 // and the fastest is kept for this shape.  The iterates do not depend on the
 // split (every piece is solved exactly), so tuning costs no extra work.
 #include <hip/hip_runtime.h>
+#include <stdint.h>
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
@@ -51,13 +52,25 @@ void plan_pieces(Plan& pl, const std::vector<Geo>& geos, size_t n_total, int wan
     pl.item_r.clear();
     pl.item_c.clear();
     pl.lds_r = pl.lds_c = 0;
+    auto want_of = [&](const Geo& g) {
+        const int w = (int)((double)want_total * (double)g.n / (double)n_total + 0.5);
+        return w < 1 ? 1 : w;
+    };
+    // work items of each sweep launch over the whole batch (latency mode is
+    // decided on those totals, not per grid)
+    long tot_r = 0, tot_c = 0;
+    for (const Geo& g : geos) {
+        const int want = want_of(g);
+        tot_r += (long)((geo_nchains(g, 0) + 63) / 64) * piece_config(g, 0, want, INT32_MAX).pieces;
+        tot_c += (long)((geo_nchains(g, 1) + 63) / 64) * piece_config(g, 1, want, INT32_MAX).pieces;
+    }
+    const int lr = (int)std::min<long>(tot_r, INT32_MAX), lc = (int)std::min<long>(tot_c, INT32_MAX);
     for (size_t gi = 0; gi < geos.size(); ++gi) {
         const Geo& g = geos[gi];
-        int want = (int)((double)want_total * (double)g.n / (double)n_total + 0.5);
-        if (want < 1) want = 1;
+        const int want = want_of(g);
         BatchGrid& t = pl.tab[gi];
-        t.cr = piece_config(g, 0, want);
-        t.cc = piece_config(g, 1, want);
+        t.cr = piece_config(g, 0, want, lr);
+        t.cc = piece_config(g, 1, want, lc);
         const int groups_r = (geo_nchains(g, 0) + 63) / 64, groups_c = (geo_nchains(g, 1) + 63) / 64;
         t.item0_r = (int)pl.item_r.size();
         pl.item_r.insert(pl.item_r.end(), (size_t)groups_r * t.cr.pieces, (int)gi);

@@ -30,12 +30,17 @@ __host__ __device__ inline int geo_nchains(const Geo& g, int axis) { return g.n 
 // positions earlier and past its end by up to `tail` positions from LDS.
 struct PieceCfg {
     int len, pieces, overlap, tail;
+    int reach_lo, reach_hi;  // LDS reserve in front of / behind the piece
 };
 
-// Pieces for a family: about `want` work items for the launch (at least 16
-// positions per piece, overlap and tail of 8 positions when cut).
-PieceCfg piece_config(const Geo& g, int axis, int want);
+// Pieces for a family: about `want` work items (16 to 64 positions per piece).
+// launch_items is the number of work items of the whole launch the family is
+// part of (0: this family alone); launches of at most kLatencyItems items run
+// about one wave per SIMD and get a longer overlap (24 instead of 8), so that
+// almost no piece has to restart its scans.
+PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items);
 constexpr int kDefaultItems = 4096;
+constexpr int kLatencyItems = 2048;
 // dynamic LDS bytes of a sweep launch with these pieces
 size_t piece_lds_bytes(const PieceCfg& cfg);
 

@@ -15,9 +15,13 @@
 // in FP64 from the segment's exact left anchor when kExact).  The scan stops
 // once the segment covering b1 - 1 is finished.
 //
-// Vals(q) returns the values of position q (r[0] scan input, r[1] weight of
-// edge q); Emit(q, c, p, last) records the result of position q: segment
-// value c and dual p of edge (q, q+1) (meaningful when kExact and not last).
+// The caller reads the values of the positions the three steps work on --
+// fill_pos(), l_pos(), u_pos() -- before the steps (all three reads can then
+// be in flight together): RingVals r[0] is the scan input, r[1] the weight of
+// the edge to the next position.  The fill only writes positions the scans
+// have finished with, so its writes never touch a value read for L or U.
+// Emit(q, c, p, last) records the result of position q: segment value c and
+// dual p of edge (q, q+1) (meaningful when kExact and not last).
 #pragma once
 
 #include "chain.hpp"
@@ -88,6 +92,12 @@ struct PieceLane {
     __device__ __forceinline__ bool fill_ready() const { return fj < b1 && (fend >= fj || qn > 0); }
     __device__ __forceinline__ bool busy() const { return scanning || fill_ready(); }
 
+    // positions whose values the next fill / step_l / step_u read (`idle`
+    // when the step will not read)
+    __device__ __forceinline__ int fill_pos(int idle) const { return fill_ready() ? fj : idle; }
+    __device__ __forceinline__ int l_pos(int idle) const { return scanning && L.k < m ? L.k : idle; }
+    __device__ __forceinline__ int u_pos(int idle) const { return scanning && bracket && U.k < m ? U.k : idle; }
+
     __device__ __forceinline__ void push(bool on, const Seg& s)
     {
         const bool to0 = on && qn == 0, to1 = on && qn == 1;
@@ -104,9 +114,9 @@ struct PieceLane {
     // wave brackets -- step_u() and resolve().  Keeping the scans in separate
     // calls lets a wave skip U once all its lanes have merged.
 
-    // write one position of the finished segments
-    template <class Vals, class Emit>
-    __device__ __forceinline__ void fill(const Vals& vals, const Emit& emit)
+    // write one position of the finished segments; rv = values at fill_pos()
+    template <class Emit>
+    __device__ __forceinline__ void fill(const RingVals<NR>& rv, const Emit& emit)
     {
         if (!fill_ready()) return;
         const bool pop = fend < fj;
@@ -117,20 +127,17 @@ struct PieceLane {
         q0.A = pop ? q1.A : q0.A;
         q0.kend = pop ? q1.kend : q0.kend;
         qn -= pop ? 1 : 0;
-        const RingVals<NR> rv = vals(fj);
         const double pr = kExact ? fp + (fc - (double)rv.r[0]) : 0.0;
         if (fj >= b0) emit(fj, fc, pr, fj == m - 1);
         fp = pr;
         ++fj;
     }
 
-    // advance L (the only scan once the bracket is resolved)
-    template <class Vals>
-    __device__ __forceinline__ void step_l(const Vals& vals)
+    // advance L (the only scan once the bracket is resolved); rv = values at l_pos()
+    __device__ __forceinline__ void step_l(const RingVals<NR>& rv)
     {
         if (!scanning || qn == 2 || (bracket && lastL > lastU)) return;
         const int k = L.k;
-        const RingVals<NR> rv = vals(k);
         Seg sg;
         const bool fin = scan_step<kExact>(L, m, rv.r[0], k + 1 < m ? rv.r[1] : 0.f, sg);
         const bool br = bracket;
@@ -143,12 +150,11 @@ struct PieceLane {
     __device__ __forceinline__ bool needs_u() const { return scanning && bracket && lastU <= lastL; }
 
 
-    template <class Vals>
-    __device__ __forceinline__ void step_u(const Vals& vals)
+    // advance U; rv = values at u_pos() (read before step_l)
+    __device__ __forceinline__ void step_u(const RingVals<NR>& rv)
     {
         if (!needs_u()) return;
         const int k = U.k;
-        const RingVals<NR> rv = vals(k);
         Seg sg;
         const bool fin = scan_step<false>(U, m, rv.r[0], k + 1 < m ? rv.r[1] : 0.f, sg);
         lastU = fin ? sg.kend : lastU;

@@ -9,22 +9,26 @@
 //
 // A work item runs in three phases, with global memory touched only in the
 // first and the last:
-//   load    the region [b0 - W, b1 + T) of the 64 chains goes to LDS with
+//   load    the window [b0 - W - 1, b1 + T) of the 64 chains goes to LDS with
 //           coalesced loads (chains along W are loaded transposed: lanes walk
-//           the positions of one row at a time); per position the scan input
-//           v (formed on the fly by the mode, e.g. 2 q1 - z - w) and the
-//           weight a of the edge to the next position;
+//           (row, position) pairs, consecutive lanes on consecutive
+//           positions); per position the scan input v (formed on the fly by
+//           the mode, e.g. 2 q1 - z - w) and the weight a of the edge to the
+//           next position;
 //   solve   every lane runs its piece from LDS and overwrites each slot it has
-//           finished with (segment value, edge dual); positions outside the
-//           region (a longer overlap after a failed bracket, a long last
-//           segment) are read from global memory;
+//           finished with (segment value, edge dual).  When some lane's last
+//           segment runs past the tail, the whole wave stages the next block
+//           at once into LDS reserved for it; positions beyond that reserve
+//           (a longer tail, or the deeper overlap after a failed bracket) are
+//           read from global memory one by one;
 //   store   the piece's results go back with coalesced accesses, combined
 //           with the mode's other arrays (e.g. z <- (z - q1) + q2).
-// No global store is in flight during the solve phase, so its occasional
-// global loads never wait for stores (on gfx9 the vector memory counter covers
-// both).
+// No global store is in flight during the solve phase, so its loads never
+// wait for stores (on gfx9 the vector memory counter covers both).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
 
 #include "chain.hpp"
 #include "launch.hpp"
@@ -219,86 +223,123 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     const int c0 = cg * kLanes;
     const int c = c0 + lane;
     const bool valid = c < nch;
+    const int nrows = nch - c0 < kLanes ? nch - c0 : kLanes;
     const Chain ch = chain_of(g, axis, valid ? c : c0);
     const int b0 = s * cfg.len;
     const int b1 = b0 + cfg.len < m ? b0 + cfg.len : m;
-    const int r0 = b0 - cfg.overlap > 0 ? b0 - cfg.overlap : 0;
-    const int r1 = b1 + cfg.tail < m ? b1 + cfg.tail : m;
-    const int rmax = cfg.overlap + cfg.len + cfg.tail;  // slots per chain
-    float* lv = lds;                // [slot][lane]: v, later segment value
-    float* la = lds + rmax * kPad;  // [slot][lane]: a, later edge dual
+    // LDS slot k holds position base + k.  The staged window [lo, hi) starts
+    // one position before the overlap (the weight of the edge in front of the
+    // scans' start) and grows at its end on demand up to hi_cap.
+    const int base = b0 - cfg.reach_lo > 0 ? b0 - cfg.reach_lo : 0;
+    const int hi_cap = b1 + cfg.reach_hi < m ? b1 + cfg.reach_hi : m;
+    const int lo = base;
+    int hi = b1 + cfg.tail < m ? b1 + cfg.tail : m;
+    const int slots = cfg.reach_lo + cfg.len + cfg.reach_hi;
+    float* lv = lds;                 // [slot][lane]: v, later segment value
+    float* la = lds + slots * kPad;  // [slot][lane]: a, later edge dual
 
-    // load: kBatch independent positions (rows) in flight before any LDS write
+    // Stage positions [qa, qb) of the 64 chains: B independent loads per lane
+    // in flight before any LDS write.  Rows are walked (row, position)
+    // flattened over the lanes, so consecutive lanes read consecutive positions.
     constexpr int kBatch = 16;
-    if (kRows) {
-        const int nrows = nch - c0 < kLanes ? nch - c0 : kLanes;
-        for (int q = r0 + lane; q - lane < r1; q += kLanes) {
-            for (int rb = 0; rb < nrows; rb += kBatch) {
-                float vv[kBatch], aa[kBatch];
+    auto stage = [&](int qa, int qb, auto batch) {
+        constexpr int B = decltype(batch)::value;
+        const int len_r = qb - qa;
+        if (len_r <= 0) return;
+        if (kRows) {
+            const int total = nrows * len_r;
+            const int drr = kLanes / len_r, dq = kLanes - drr * len_r;
+            int rr = lane / len_r, q = lane - rr * len_r;  // element lane + kLanes * t
+            for (int t0 = 0; t0 * kLanes < total; t0 += B) {
+                float vv[B], aa[B];
+                int r2 = rr, q2 = q;
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const int rr = rb + u;
-                    if (rr < nrows && q < r1) {
-                        const int i = (c0 + rr) * g.W + q;
+                for (int u = 0; u < B; ++u) {
+                    if (rr < nrows) {
+                        const int i = (c0 + rr) * g.W + qa + q;
+                        vv[u] = mode.v_at(i);
+                        aa[u] = mode.a_at(i);
+                    }
+                    rr += drr;
+                    q += dq;
+                    if (q >= len_r) {
+                        q -= len_r;
+                        ++rr;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    if (r2 < nrows) {
+                        const int sl = (qa + q2 - base) * kPad + r2;
+                        lv[sl] = vv[u];
+                        la[sl] = aa[u];
+                    }
+                    r2 += drr;
+                    q2 += dq;
+                    if (q2 >= len_r) {
+                        q2 -= len_r;
+                        ++r2;
+                    }
+                }
+            }
+        } else if (valid) {
+            for (int qb0 = qa; qb0 < qb; qb0 += B) {
+                float vv[B], aa[B];
+#pragma unroll
+                for (int u = 0; u < B; ++u) {
+                    const int q = qb0 + u;
+                    if (q < qb) {
+                        const int i = ch.base + q * ch.stride;
                         vv[u] = mode.v_at(i);
                         aa[u] = mode.a_at(i);
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
-                    const int rr = rb + u;
-                    if (rr < nrows && q < r1) {
-                        lv[(q - r0) * kPad + rr] = vv[u];
-                        la[(q - r0) * kPad + rr] = aa[u];
+                for (int u = 0; u < B; ++u) {
+                    const int q = qb0 + u;
+                    if (q < qb) {
+                        lv[(q - base) * kPad + lane] = vv[u];
+                        la[(q - base) * kPad + lane] = aa[u];
                     }
                 }
             }
         }
-    } else if (valid) {
-        for (int qb = r0; qb < r1; qb += kBatch) {
-            float vv[kBatch], aa[kBatch];
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const int q = qb + u;
-                if (q < r1) {
-                    const int i = ch.base + q * ch.stride;
-                    vv[u] = mode.v_at(i);
-                    aa[u] = mode.a_at(i);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
-                const int q = qb + u;
-                if (q < r1) {
-                    lv[(q - r0) * kPad + lane] = vv[u];
-                    la[(q - r0) * kPad + lane] = aa[u];
-                }
-            }
-        }
-    }
-    wave_fence();
+        wave_fence();
+    };
+    using Big = std::integral_constant<int, kBatch>;
+    using Small = std::integral_constant<int, 8>;
+    stage(lo, hi, Big{});
 
-    // solve
+    // solve; positions outside the window (beyond the reserve) come from global memory
     auto vals = [&](int q) -> RingVals<2> {
-        if (q >= r0 && q < r1) return {{lv[(q - r0) * kPad + lane], la[(q - r0) * kPad + lane]}};
+        if (q >= lo && q < hi) return {{lv[(q - base) * kPad + lane], la[(q - base) * kPad + lane]}};
         const int i = ch.base + q * ch.stride;
         return {{mode.v_at(i), mode.a_at(i)}};
     };
     auto a_before = [&](int q) -> float {
-        return (q >= r0 && q < r1) ? la[(q - r0) * kPad + lane] : mode.a_at(ch.base + q * ch.stride);
+        return (q >= lo && q < hi) ? la[(q - base) * kPad + lane] : mode.a_at(ch.base + q * ch.stride);
     };
     auto emit = [&](int q, double cv, double pr, bool last) {
-        const int sl = (q - r0) * kPad + lane;
+        const int sl = (q - base) * kPad + lane;
         lv[sl] = (float)cv;
         if (kExact) la[sl] = last ? 0.f : clip_dual(pr, la[sl]);
     };
+    constexpr int kGrow = 8;
     PieceLane<2, kExact> pl;
     pl.begin(valid, m, b0, b1, cfg.overlap > 0 ? cfg.overlap : 1, a_before);
     while (__any(pl.busy())) {
-        pl.fill(vals, emit);
-        pl.step_l(vals);
+        // some lane's scan is about to read past the window: stage the next block
+        if (hi < hi_cap && __any(pl.scanning && pl.L.k >= hi)) {
+            const int nh = hi + kGrow < hi_cap ? hi + kGrow : hi_cap;
+            stage(hi, nh, Small{});
+            hi = nh;
+        }
+        // the three reads of this iteration, issued together
+        const RingVals<2> rf = vals(pl.fill_pos(lo)), rl = vals(pl.l_pos(lo)), ru = vals(pl.u_pos(lo));
+        pl.fill(rf, emit);
+        pl.step_l(rl);
         if (__any(pl.bracket && pl.scanning)) {
-            pl.step_u(vals);
+            pl.step_u(ru);
             pl.resolve(a_before);
         }
     }
@@ -306,12 +347,20 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
 
     // store
     if (kRows) {
-        const int nrows = nch - c0 < kLanes ? nch - c0 : kLanes;
-        for (int q = b0 + lane; q - lane < b1; q += kLanes) {
-            if (q < b1) {
-                for (int rr = 0; rr < nrows; ++rr)
-                    mode.store((c0 + rr) * g.W + q, lv[(q - r0) * kPad + rr],
-                               kExact ? la[(q - r0) * kPad + rr] : 0.f);
+        const int len_r = b1 - b0;
+        const int total = nrows * len_r;
+        const int drr = kLanes / len_r, dq = kLanes - drr * len_r;
+        int rr = lane / len_r, q = lane - rr * len_r;
+        for (int t = 0; t * kLanes < total; ++t) {
+            if (rr < nrows) {
+                const int sl = (b0 + q - base) * kPad + rr;
+                mode.store((c0 + rr) * g.W + b0 + q, lv[sl], kExact ? la[sl] : 0.f);
+            }
+            rr += drr;
+            q += dq;
+            if (q >= len_r) {
+                q -= len_r;
+                ++rr;
             }
         }
     } else if (valid) {
@@ -320,8 +369,8 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 const int q = qb + u;
-                cv[u] = q < b1 ? lv[(q - r0) * kPad + lane] : 0.f;
-                pv[u] = (kExact && q < b1) ? la[(q - r0) * kPad + lane] : 0.f;
+                cv[u] = q < b1 ? lv[(q - base) * kPad + lane] : 0.f;
+                pv[u] = (kExact && q < b1) ? la[(q - base) * kPad + lane] : 0.f;
             }
             typename M::Pre pre[kBatch];
 #pragma unroll
@@ -365,7 +414,7 @@ inline int items_of(const Geo& g, int axis, const PieceCfg& cfg)
 
 inline size_t lds_bytes(const PieceCfg& cfg)
 {
-    return sizeof(float) * 2 * (size_t)(cfg.overlap + cfg.len + cfg.tail) * kPad;
+    return sizeof(float) * 2 * (size_t)(cfg.reach_lo + cfg.len + cfg.reach_hi) * kPad;
 }
 
 template <class M, bool kExact>
@@ -382,7 +431,7 @@ hipError_t launch_mode_x(const Geo& g, int axis, const M& mode, const PieceCfg& 
 template <class M>
 hipError_t launch_mode(const Geo& g, int axis, const M& mode, bool duals, hipStream_t s)
 {
-    const PieceCfg cfg = piece_config(g, axis, kDefaultItems);
+    const PieceCfg cfg = piece_config(g, axis, kDefaultItems, 0);
     return duals ? launch_mode_x<M, true>(g, axis, mode, cfg, s)
                  : launch_mode_x<M, false>(g, axis, mode, cfg, s);
 }
@@ -428,20 +477,35 @@ hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, 
 size_t piece_lds_bytes(const PieceCfg& cfg) { return lds_bytes(cfg); }
 
 
-PieceCfg piece_config(const Geo& g, int axis, int want)
+PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items)
 {
-    // about `want` work items, pieces of at least 16 positions
+    // about `want` work items, pieces of 16 to kMaxLen positions (a work item's
+    // LDS, 2 x (reach_lo + len + reach_hi) x 65 floats, stays below 64 KiB)
+    constexpr int kMaxLen = 64;
     const int m = geo_extent(g, axis);
     const int groups = (geo_nchains(g, axis) + kLanes - 1) / kLanes;
     if (want < 1) want = 1;
     int pieces = (want + groups - 1) / groups;
     int len = (m + pieces - 1) / pieces;
     len = len < 16 ? 16 : ((len + 15) / 16) * 16;
+    len = len < kMaxLen ? len : kMaxLen;
     PieceCfg cfg;
     cfg.len = len < m ? len : m;
     cfg.pieces = (m + cfg.len - 1) / cfg.len;
-    cfg.overlap = cfg.pieces > 1 ? 8 : 0;
-    cfg.tail = cfg.pieces > 1 ? 8 : 0;
+    const bool cut = cfg.pieces > 1;
+    // With few work items (about one wave per SIMD) the slowest wave sets the
+    // launch time, and one lane whose bracket fails doubles its wave's work:
+    // scan from further back so that almost no piece restarts.  With many
+    // work items waves overlap and the total work counts: keep the overlap
+    // short and LDS small (more waves resident).
+    const long items = launch_items > 0 ? launch_items : (long)groups * cfg.pieces;
+    const bool latency_bound = items <= kLatencyItems;
+    cfg.overlap = cut ? (latency_bound ? 24 : 8) : 0;
+    cfg.tail = cut ? 8 : 0;
+    // LDS: the overlap plus the weight of the edge in front of it, the piece,
+    // and the tail plus one block of growth
+    cfg.reach_lo = cut ? cfg.overlap + 1 : 0;
+    cfg.reach_hi = cut ? cfg.tail + 8 : 0;
     return cfg;
 }
 
@@ -474,7 +538,13 @@ hipError_t launch_drp_sweeps(const Geo& g, int nfam, const float* z, const float
     if (nfam == 1) return launch_mode(g, 0, m0, p != nullptr, s);
     if (nfam != 2) return hipErrorInvalidValue;
     ModeSweepP m1{z + n, a[1], q + n, p ? p + n : nullptr};
-    const PieceCfg c0 = piece_config(g, 0, kDefaultItems), c1 = piece_config(g, 1, kDefaultItems);
+    PieceCfg c0 = piece_config(g, 0, kDefaultItems, 0), c1 = piece_config(g, 1, kDefaultItems, 0);
+    {
+        // one launch holds both families: decide latency mode on its total
+        const int tot = items_of(g, 0, c0) + items_of(g, 1, c1);
+        c0 = piece_config(g, 0, kDefaultItems, tot);
+        c1 = piece_config(g, 1, kDefaultItems, tot);
+    }
     const int n0 = items_of(g, 0, c0), n1 = items_of(g, 1, c1);
     const size_t shm = lds_bytes(c0) > lds_bytes(c1) ? lds_bytes(c0) : lds_bytes(c1);
     if (p)

@@ -97,6 +97,28 @@ def test_prox_axes_parity(dev, shape, axis):
     assert rel_linf(x.cpu().numpy(), xr) <= REL_TOL
 
 
+@pytest.mark.parametrize("shape,axis", [((4160, 8192), 0), ((8192, 4160), 1)])
+def test_prox_long_chains_sampled(dev, shape, axis):
+    """Chains long enough that the piece length hits its cap, 65 chain groups:
+    sampled chains against the oracle (the whole grid is too large for it)."""
+    from paper_1503_01563_amd import mc
+    rng = np.random.default_rng(17 + axis)
+    v = (rng.normal(size=shape) * 4).astype(np.float32)
+    a = rng.uniform(0, 3, size=shape).astype(np.float32)
+    if axis == 0:
+        a[:, -1] = 0
+    else:
+        a[-1, :] = 0
+    x = mc.tv_prox_chains(to_dev(v, dev), to_dev(a, dev), axis).cpu().numpy()
+    nch = shape[axis]
+    for c in list(rng.choice(nch, 12, replace=False)) + [0, nch - 1]:
+        vc = v[c] if axis == 0 else v[:, c]
+        ac = a[c] if axis == 0 else a[:, c]
+        xc = x[c] if axis == 0 else x[:, c]
+        xr, _ = oracle.tv1d(vc.astype(np.float64), ac[:-1].astype(np.float64))
+        assert rel_linf(xc, xr) <= REL_TOL, c
+
+
 @pytest.mark.parametrize("shape", [(64, 64), (37, 53), (1, 300), (300, 1), (9, 11, 13), (1, 1)])
 def test_cut_energy_bit_exact(dev, shape):
     from paper_1503_01563_amd import mc
