@@ -58,7 +58,8 @@ int make_geo(const mc_grid* grid, Geo* g)
 
 void free_ws(mc_ctx* c)
 {
-    hipFree(c->z); hipFree(c->z2); hipFree(c->y); hipFree(c->p); hipFree(c->xt);
+    // release errors are not actionable here; the pointers are dropped either way
+    for (float* q : {c->z, c->z2, c->y, c->p, c->xt}) (void)hipFree(q);
     c->z = c->z2 = c->y = c->p = c->xt = nullptr;
     c->cap_n = 0;
     c->cap_r = 0;
@@ -195,19 +196,20 @@ int mc_ctx_create(mc_ctx** out, int device)
 int mc_ctx_destroy(mc_ctx* c)
 {
     if (!c) return MC_OK;
-    hipSetDevice(c->device);
-    hipDeviceSynchronize();
+    // teardown: errors are not actionable, every resource is released regardless
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
     free_ws(c);
-    hipFree(c->partials);
-    hipFree(c->dout);
-    if (c->hout) hipHostFree(c->hout);
-    if (c->ev0) hipEventDestroy(c->ev0);
-    if (c->ev1) hipEventDestroy(c->ev1);
-    for (hipEvent_t e : c->prof_ev) hipEventDestroy(e);
-    hipFree(c->bbuf);
-    hipFree(c->bmeta);
-    hipFree(c->nbuf);
-    if (c->bstream) hipStreamDestroy(c->bstream);
+    (void)hipFree(c->partials);
+    (void)hipFree(c->dout);
+    if (c->hout) (void)hipHostFree(c->hout);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
+    (void)hipFree(c->bbuf);
+    (void)hipFree(c->bmeta);
+    (void)hipFree(c->nbuf);
+    if (c->bstream) (void)hipStreamDestroy(c->bstream);
     delete c;
     return MC_OK;
 }

@@ -99,7 +99,7 @@ int reserve_meta(mc_ctx* c, size_t total, hipStream_t s)
 {
     if (total <= c->bmeta_cap) return MC_OK;
     MC_HIP(hipStreamSynchronize(s));
-    hipFree(c->bmeta);
+    (void)hipFree(c->bmeta);  // the old buffer is dropped either way
     c->bmeta = nullptr;
     c->bmeta_cap = 0;
     if (hipMalloc(&c->bmeta, total) != hipSuccess) {
@@ -192,7 +192,7 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
     hipStream_t s = c->bstream;
     if (floats > c->bcap) {
         MC_HIP(hipDeviceSynchronize());
-        hipFree(c->bbuf);
+        (void)hipFree(c->bbuf);  // the old buffer is dropped either way
         c->bbuf = nullptr;
         c->bcap = 0;
         if (hipMalloc(&c->bbuf, floats * sizeof(float)) != hipSuccess) {
@@ -320,8 +320,8 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
         all_done = true;
         for (const BatchGrid& t : host_tab) all_done = all_done && t.done;
     }
-    hipGraphExecDestroy(exec);
-    hipGraphDestroy(graph);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
     if (graph_err) return graph_err;
 
     MC_HIP(launch_batch_labels(bl, o.tau0, s));

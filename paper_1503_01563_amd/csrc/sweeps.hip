@@ -310,12 +310,20 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     using Small = std::integral_constant<int, 8>;
     stage(lo, hi, Big{});
 
-    // solve; positions outside the window (beyond the reserve) come from global memory
-    auto vals = [&](int q) -> RingVals<2> {
-        if (q >= lo && q < hi) return {{lv[(q - base) * kPad + lane], la[(q - base) * kPad + lane]}};
+    // solve.  Values are read from LDS at an index clamped into the window;
+    // only when some lane needs a position outside it (beyond the reserve) does
+    // the wave take a separate path that reads those from global memory.
+    // Keeping the two paths apart keeps the common reads plain LDS loads.
+    auto lds_at = [&](int q) -> RingVals<2> {
+        const int qc = q < lo ? lo : (q >= hi ? hi - 1 : q);
+        const int sl = (qc - base) * kPad + lane;
+        return {{lv[sl], la[sl]}};
+    };
+    auto glob_at = [&](int q) -> RingVals<2> {
         const int i = ch.base + q * ch.stride;
         return {{mode.v_at(i), mode.a_at(i)}};
     };
+    auto inside = [&](int q) { return q >= lo && q < hi; };
     auto a_before = [&](int q) -> float {
         return (q >= lo && q < hi) ? la[(q - base) * kPad + lane] : mode.a_at(ch.base + q * ch.stride);
     };
@@ -335,7 +343,13 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
             hi = nh;
         }
         // the three reads of this iteration, issued together
-        const RingVals<2> rf = vals(pl.fill_pos(lo)), rl = vals(pl.l_pos(lo)), ru = vals(pl.u_pos(lo));
+        const int qf = pl.fill_pos(lo), ql = pl.l_pos(lo), qu = pl.u_pos(lo);
+        RingVals<2> rf = lds_at(qf), rl = lds_at(ql), ru = lds_at(qu);
+        if (__any(!inside(qf) || !inside(ql) || !inside(qu))) {
+            if (!inside(qf)) rf = glob_at(qf);
+            if (!inside(ql)) rl = glob_at(ql);
+            if (!inside(qu)) ru = glob_at(qu);
+        }
         pl.fill(rf, emit);
         pl.step_l(rl);
         if (__any(pl.bracket && pl.scanning)) {
@@ -503,9 +517,10 @@ PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items)
     cfg.overlap = cut ? (latency_bound ? 24 : 8) : 0;
     cfg.tail = cut ? 8 : 0;
     // LDS: the overlap plus the weight of the edge in front of it, the piece,
-    // and the tail plus one block of growth
+    // and the tail -- plus one block of tail growth when latency bound (with
+    // many work items, LDS per wave sets how many waves are resident)
     cfg.reach_lo = cut ? cfg.overlap + 1 : 0;
-    cfg.reach_hi = cut ? cfg.tail + 8 : 0;
+    cfg.reach_hi = cut ? cfg.tail + (latency_bound ? 8 : 0) : 0;
     return cfg;
 }
 
