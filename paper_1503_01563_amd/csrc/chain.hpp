@@ -38,6 +38,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mc {
 
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -59,9 +61,15 @@ __device__ __forceinline__ float clip_dual(double p, float a)
     return fminf(fmaxf((float)p, -a), a);
 }
 
+// Segment values are FP64 when edge duals are wanted (the duals are carried
+// from them), FP32 otherwise (only FP32 values are emitted).
+template <bool kExact>
+using SegVal = std::conditional_t<kExact, double, float>;
+
 // A finished segment ending at kend, of value c, entered with dual A.
+template <bool kExact>
 struct Seg {
-    double c;
+    SegVal<kExact> c;
     float A;
     int kend;
 };
@@ -105,10 +113,12 @@ __device__ __forceinline__ void scan_open(Scan& s, float vk, float ak)
 }
 
 template <bool kExact>
-__device__ __forceinline__ double seg_value(float vref, double num, int len)
+__device__ __forceinline__ SegVal<kExact> seg_value(float vref, double num, int len)
 {
-    return kExact ? (double)vref + div_by_len(num, (double)len)
-                  : (double)(vref + (float)num * fast_rcp((float)len));
+    if constexpr (kExact)
+        return (double)vref + div_by_len(num, (double)len);
+    else
+        return vref + (float)num * fast_rcp((float)len);
 }
 
 // One step at position s.k with vk = v(s.k), ak = weight of edge s.k (0 for
@@ -118,7 +128,7 @@ __device__ __forceinline__ double seg_value(float vref, double num, int len)
 // lane takes costs all lanes, and the state updates of the three cases (open,
 // extend, knot) are cheap next to the exec-mask bookkeeping of branches.
 template <bool kExact>
-__device__ __forceinline__ bool scan_step(Scan& s, int m, float vk, float ak, Seg& out)
+__device__ __forceinline__ bool scan_step(Scan& s, int m, float vk, float ak, Seg<kExact>& out)
 {
     const bool opening = s.k == s.k0;
     const bool last = s.k == m - 1;

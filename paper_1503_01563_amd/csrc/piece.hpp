@@ -43,8 +43,9 @@ struct PieceLane {
     float ancL, ancU;  // dual of the edge at that knot
     // fill
     int fj, fend;  // next position to write, end of the segment being written
-    double fc, fp;  // its value, dual of the edge left of fj
-    Seg q0, q1;     // queued finished segments
+    using V = SegVal<kExact>;
+    V fc, fp;                // its value, dual of the edge left of fj
+    Seg<kExact> q0, q1;      // queued finished segments
     int qn;
 
     // (Re)start the scans from p0 = max(0, b0 - W); a_before(q) is the weight
@@ -55,8 +56,8 @@ struct PieceLane {
         const int p0 = b0 - W > 0 ? b0 - W : 0;
         qn = 0;
         fend = -1;
-        fc = 0.0;
-        fp = 0.0;
+        fc = V(0);
+        fp = V(0);
         lastL = lastU = -1;
         ancL = ancU = 0.f;
         if (p0 == 0) {
@@ -98,7 +99,7 @@ struct PieceLane {
     __device__ __forceinline__ int l_pos(int idle) const { return scanning && L.k < m ? L.k : idle; }
     __device__ __forceinline__ int u_pos(int idle) const { return scanning && bracket && U.k < m ? U.k : idle; }
 
-    __device__ __forceinline__ void push(bool on, const Seg& s)
+    __device__ __forceinline__ void push(bool on, const Seg<kExact>& s)
     {
         const bool to0 = on && qn == 0, to1 = on && qn == 1;
         q0.c = to0 ? s.c : q0.c;
@@ -121,13 +122,13 @@ struct PieceLane {
         if (!fill_ready()) return;
         const bool pop = fend < fj;
         fc = pop ? q0.c : fc;
-        fp = pop ? (double)q0.A : fp;
+        fp = pop ? (V)q0.A : fp;
         fend = pop ? q0.kend : fend;
         q0.c = pop ? q1.c : q0.c;
         q0.A = pop ? q1.A : q0.A;
         q0.kend = pop ? q1.kend : q0.kend;
         qn -= pop ? 1 : 0;
-        const double pr = kExact ? fp + (fc - (double)rv.r[0]) : 0.0;
+        const V pr = kExact ? fp + (fc - (V)rv.r[0]) : V(0);
         if (fj >= b0) emit(fj, fc, pr, fj == m - 1);
         fp = pr;
         ++fj;
@@ -138,7 +139,7 @@ struct PieceLane {
     {
         if (!scanning || qn == 2 || (bracket && lastL > lastU)) return;
         const int k = L.k;
-        Seg sg;
+        Seg<kExact> sg;
         const bool fin = scan_step<kExact>(L, m, rv.r[0], k + 1 < m ? rv.r[1] : 0.f, sg);
         const bool br = bracket;
         lastL = fin && br ? sg.kend : lastL;
@@ -155,7 +156,7 @@ struct PieceLane {
     {
         if (!needs_u()) return;
         const int k = U.k;
-        Seg sg;
+        Seg<false> sg;
         const bool fin = scan_step<false>(U, m, rv.r[0], k + 1 < m ? rv.r[1] : 0.f, sg);
         lastU = fin ? sg.kend : lastU;
         ancU = fin ? U.A : ancU;

@@ -239,7 +239,8 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     float* la = lds + slots * kPad;  // [slot][lane]: a, later edge dual
 
     // Stage positions [qa, qb) of the 64 chains: B independent loads per lane
-    // in flight before any LDS write.  Rows are walked (row, position)
+    // in flight before any LDS write (more for the initial window, when the
+    // scan state is not live yet, 8 for growth inside the solve loop).  Rows are walked (row, position)
     // flattened over the lanes, so consecutive lanes read consecutive positions.
     constexpr int kBatch = 16;
     auto stage = [&](int qa, int qb, auto batch) {
@@ -306,7 +307,8 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
         }
         wave_fence();
     };
-    using Big = std::integral_constant<int, kBatch>;
+    // rows load two arrays per element, the column modes up to four
+    using Big = std::integral_constant<int, kRows ? 2 * kBatch : kBatch>;
     using Small = std::integral_constant<int, 8>;
     stage(lo, hi, Big{});
 
@@ -327,10 +329,10 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     auto a_before = [&](int q) -> float {
         return (q >= lo && q < hi) ? la[(q - base) * kPad + lane] : mode.a_at(ch.base + q * ch.stride);
     };
-    auto emit = [&](int q, double cv, double pr, bool last) {
+    auto emit = [&](int q, auto cv, auto pr, bool last) {
         const int sl = (q - base) * kPad + lane;
         lv[sl] = (float)cv;
-        if (kExact) la[sl] = last ? 0.f : clip_dual(pr, la[sl]);
+        if constexpr (kExact) la[sl] = last ? 0.f : clip_dual(pr, la[sl]);
     };
     constexpr int kGrow = 8;
     PieceLane<2, kExact> pl;
@@ -344,6 +346,8 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
         }
         // the three reads of this iteration, issued together
         const int qf = pl.fill_pos(lo), ql = pl.l_pos(lo), qu = pl.u_pos(lo);
+        // (after a restart the scans, and the fill that carries the duals
+        // forward from their merge knot, can start in front of the window)
         RingVals<2> rf = lds_at(qf), rl = lds_at(ql), ru = lds_at(qu);
         if (__any(!inside(qf) || !inside(ql) || !inside(qu))) {
             if (!inside(qf)) rf = glob_at(qf);
