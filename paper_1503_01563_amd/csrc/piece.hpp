@@ -20,8 +20,9 @@
 // be in flight together): RingVals r[0] is the scan input, r[1] the weight of
 // the edge to the next position.  The fill only writes positions the scans
 // have finished with, so its writes never touch a value read for L or U.
-// Emit(q, c, p, last) records the result of position q: segment value c and
-// dual p of edge (q, q+1) (meaningful when kExact and not last).
+// Emit(q, c, p, last, on) records the result of position q when `on`: segment
+// value c and dual p of edge (q, q+1) (meaningful when kExact and not last);
+// it is called on every fill step and must discard the write when !on.
 #pragma once
 
 #include "chain.hpp"
@@ -119,8 +120,10 @@ struct PieceLane {
     template <class Emit>
     __device__ __forceinline__ void fill(const RingVals<NR>& rv, const Emit& emit)
     {
-        if (!fill_ready()) return;
-        const bool pop = fend < fj;
+        // branch-free, so that its instructions can fill the stalls of the
+        // scan's dependency chain; Emit gets whether the write is real
+        const bool go = fill_ready();
+        const bool pop = go && fend < fj;
         fc = pop ? q0.c : fc;
         fp = pop ? (V)q0.A : fp;
         fend = pop ? q0.kend : fend;
@@ -129,9 +132,9 @@ struct PieceLane {
         q0.kend = pop ? q1.kend : q0.kend;
         qn -= pop ? 1 : 0;
         const V pr = kExact ? fp + (fc - (V)rv.r[0]) : V(0);
-        if (fj >= b0) emit(fj, fc, pr, fj == m - 1);
-        fp = pr;
-        ++fj;
+        emit(fj, fc, pr, fj == m - 1, go && fj >= b0);
+        fp = go ? pr : fp;
+        fj += go ? 1 : 0;
     }
 
     // advance L (the only scan once the bracket is resolved); rv = values at l_pos()

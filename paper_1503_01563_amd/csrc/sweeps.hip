@@ -235,8 +235,9 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     const int lo = base;
     int hi = b1 + cfg.tail < m ? b1 + cfg.tail : m;
     const int slots = cfg.reach_lo + cfg.len + cfg.reach_hi;
-    float* lv = lds;                 // [slot][lane]: v, later segment value
-    float* la = lds + slots * kPad;  // [slot][lane]: a, later edge dual
+    // one extra row per array takes the writes of lanes with nothing to emit
+    float* lv = lds;                       // [slot][lane]: v, later segment value
+    float* la = lds + (slots + 1) * kPad;  // [slot][lane]: a, later edge dual
 
     // Stage positions [qa, qb) of the 64 chains: B independent loads per lane
     // in flight before any LDS write (more for the initial window, when the
@@ -329,8 +330,8 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     auto a_before = [&](int q) -> float {
         return (q >= lo && q < hi) ? la[(q - base) * kPad + lane] : mode.a_at(ch.base + q * ch.stride);
     };
-    auto emit = [&](int q, auto cv, auto pr, bool last) {
-        const int sl = (q - base) * kPad + lane;
+    auto emit = [&](int q, auto cv, auto pr, bool last, bool on) {
+        const int sl = (on ? q - base : slots) * kPad + lane;
         lv[sl] = (float)cv;
         if constexpr (kExact) la[sl] = last ? 0.f : clip_dual(pr, la[sl]);
     };
@@ -432,7 +433,7 @@ inline int items_of(const Geo& g, int axis, const PieceCfg& cfg)
 
 inline size_t lds_bytes(const PieceCfg& cfg)
 {
-    return sizeof(float) * 2 * (size_t)(cfg.reach_lo + cfg.len + cfg.reach_hi) * kPad;
+    return sizeof(float) * 2 * (size_t)(cfg.reach_lo + cfg.len + cfg.reach_hi + 1) * kPad;
 }
 
 template <class M, bool kExact>
