@@ -29,6 +29,32 @@ if ROOT not in sys.path:
 METRIC = "chain-prox voxel-sweeps/s (%HBM peak); time-to-exact-cut cold vs warm start"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_VOXEL_SWEEP = 16.0  # two-set DR: 32 B per voxel-iteration over two sweeps
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "image2d_1024_sweep_traffic.md")
+SWEEP_SOURCES = ["chain.hpp", "piece.hpp", "sweeps.hip", "launch.hpp"]
+
+
+def sweep_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_1503_01563_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed counter summary, or None
+    when the sweep kernels changed since the counters were taken."""
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"sweep sources sha256\[:16\]: `([0-9a-f]+)`", text)
+    m_val = re.search(r"HBM bytes per sweep launch: `([0-9.eE+]+)`", text)
+    if not m_hash or not m_val or m_hash.group(1) != sweep_sources_hash():
+        return None
+    return float(m_val.group(1))
 
 
 def parse():
@@ -44,6 +70,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warm-grids", type=int, default=16,
                     help="held-out 512x512 grids for the cold vs warm-start comparison (0: skip)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed steps, copy 256 MiB device to device (a reference "
+                         "kernel for the HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
@@ -107,8 +136,14 @@ def main():
                                    profile=True))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    if args.calibrate_copy:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
-    sweeps = sum(n * r * res.iters for res in results)
+    sweeps = sum(n * res.sweep_launches for res in results)  # sweeps actually run
     sweep_ms = sum(res.sweep_ms for res in results)
     launches = sum(res.sweep_launches for res in results)
     avg_launch_s = sweep_ms / 1e3 / max(launches, 1)
@@ -145,7 +180,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "kernel": "k_sweep<ModeRows2> + k_sweep<ModeCols2> (chain-prox sweeps)",
             "avg_launch_us": 1e6 * avg_launch_s,
             "bytes_per_launch": bytes_per_launch,

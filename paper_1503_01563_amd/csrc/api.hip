@@ -300,7 +300,21 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     while (it < o.max_iters) {
         ++it;
         const bool check = (it % o.check_every == 0) || it == o.max_iters;
-        if (two_set) {
+        // A cold start begins at z = 0, whose chain proxes are 0 with zero
+        // duals (the prox of a constant chain is the chain itself).  Sweeping
+        // that is slow -- every chain is one segment, so no bracket closes
+        // before the chain start -- and unnecessary: set the results instead.
+        const bool cold_first = it == 1 && !z0;
+        if (two_set && cold_first) {
+            MC_HIP(hipMemsetAsync(c->y, 0, sizeof(float) * n, s));
+            if (check) MC_HIP(hipMemsetAsync(c->p, 0, sizeof(float) * n, s));
+            MC_HIP(tm.begin(s));
+            MC_HIP(launch_dr2_cols(g, c->y, zc, zn, w, a[1], check ? c->p + n : nullptr, s));
+            MC_HIP(tm.end(s));
+        } else if (cold_first) {
+            if (check) MC_HIP(hipMemsetAsync(c->p, 0, sizeof(float) * (size_t)r * n, s));
+            MC_HIP(launch_cold_product(g, r, w, zn, s));
+        } else if (two_set) {
             MC_HIP(tm.begin(s));
             MC_HIP(launch_dr2_rows(g, zc, a[0], c->y, check ? c->p : nullptr, s));
             MC_HIP(tm.end(s));

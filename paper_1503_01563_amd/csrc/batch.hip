@@ -261,6 +261,14 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
     BatchLaunch bl;
     double* partials = nullptr;
     int it = 0;  // iterations done
+    // the first iteration from z = 0 (row proxes 0), on the plan of the first
+    // candidate; it is not timed by the autotuner (it sweeps only the columns)
+    if (o.max_iters > 1) {
+        plan_pieces(pl, geos, n_total, items > 0 ? items : kCandidates[0]);
+        if ((rc = upload(c, pl, s, &bl, &partials))) return rc;
+        MC_HIP(launch_batch_iteration(bl, 0, false, s, true));
+        ++it;
+    }
     if (items == 0) {
         // autotune on the first iterations of the solve itself
         float best_ms = INFINITY;
@@ -280,12 +288,12 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
             }
             ++it;
         }
-        if (it & 1) {  // keep an even iteration count before the graph
-            MC_HIP(launch_batch_iteration(bl, it & 1, false, s));
-            ++it;
-        }
         items = best;
         c->tuned_items[sig] = best;
+    }
+    if ((it & 1) && it < o.max_iters) {  // an even iteration count before the graph (its parity)
+        MC_HIP(launch_batch_iteration(bl, it & 1, false, s));
+        ++it;
     }
     plan_pieces(pl, geos, n_total, items);
     if ((rc = upload(c, pl, s, &bl, &partials))) return rc;
@@ -305,7 +313,8 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
     std::vector<BatchGrid> host_tab((size_t)n_grids);
     bool all_done = false;
     int graph_err = MC_OK;
-    while (it < o.max_iters && !all_done) {
+    // at least one replay: every grid gets a certificate and a primal to label
+    for (bool first = true; first || (it < o.max_iters && !all_done); first = false) {
         if (launch_set_int(iter_dev, it + K, s) != hipSuccess || hipGraphLaunch(exec, s) != hipSuccess) {
             graph_err = hip_error(hipGetLastError(), "batch graph replay");
             break;

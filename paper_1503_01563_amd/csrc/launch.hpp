@@ -80,6 +80,10 @@ hipError_t launch_drp_sweeps(const Geo& g, int nfam, const float* z, const float
 hipError_t launch_drp_final(const Geo& g, int r, const float* z, float* znew, const float* q,
                             const float* a_last, const float* w, float* p_last, hipStream_t s);
 
+// Product space, first iteration from z = 0 (all proxes vanish):
+// zn_j = -(w * (1/r)) for j < r.
+hipError_t launch_cold_product(const Geo& g, int r, const float* w, float* zn, hipStream_t s);
+
 // Certificate from the edge duals p: primal xc = -w - sum_j D_j^T p_j (FP32
 // out), then out[kCertValues] = {E(S_t) for the ladder, TV gap, LB} in FP64.
 // partials needs kCertValues * kReduceBlocks doubles.
@@ -124,7 +128,10 @@ struct BatchLaunch {
 
 // One two-set iteration over every unfinished grid; parity selects the state
 // buffer read.  With duals, the row/column duals are written for the check.
-hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, hipStream_t s);
+// cold: the first iteration from z = 0, whose row proxes are 0 (q1 is zeroed
+// instead of swept; no duals are written for the rows).
+hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, hipStream_t s,
+                                  bool cold = false);
 // Certificate of every unfinished grid: grids whose certificate is below
 // gap_tol are marked done at iteration *iter_dev.
 hipError_t launch_batch_check(const BatchLaunch& b, float tau0, double gap_tol, const int* iter_dev,

@@ -269,6 +269,18 @@ __global__ void __launch_bounds__(kReduceThreads) k_batch_labels(BatchLaunch b, 
 
 __global__ void k_set_int(int* dst, int v) { *dst = v; }
 
+// First product-space iteration from z = 0: every prox of 0 is 0, so
+// z_j' = y_j - (2Y - Z - u)/r = -(w * (1/r)) for every family j (the same FP32
+// expression the fused final sweep evaluates).
+__global__ void k_cold_product(const float* __restrict__ w, int n, int r, float* __restrict__ zn)
+{
+    const float inv = 1.f / (float)r;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float v = -(w[i] * inv);
+        for (int j = 0; j < r; ++j) zn[(size_t)j * n + i] = v;
+    }
+}
+
 __global__ void k_stamp(unsigned long long* dst) { *dst = wall_clock64(); }
 
 __global__ void __launch_bounds__(kReduceThreads)
@@ -384,6 +396,13 @@ hipError_t launch_batch_labels(const BatchLaunch& b, float tau0, hipStream_t s)
     Taus tz;
     tau_ladder(tau0, tz.t);
     hipLaunchKernelGGL(k_batch_labels, dim3(b.blocks), dim3(kReduceThreads), 0, s, b, tz);
+    return hipGetLastError();
+}
+
+hipError_t launch_cold_product(const Geo& g, int r, const float* w, float* zn, hipStream_t s)
+{
+    const int blocks = (g.n + 255) / 256 < 2048 ? (g.n + 255) / 256 : 2048;
+    hipLaunchKernelGGL(k_cold_product, dim3(blocks), dim3(256), 0, s, w, g.n, r, zn);
     return hipGetLastError();
 }
 
