@@ -347,17 +347,22 @@ __global__ void __launch_bounds__(kThreads) k_wgrad(SrcIn in, SrcG gsrc, float* 
     }
 }
 
-// grad_W[co][k] and grad_b[co] as fixed-order sums of the partials.
+// grad_W[co][k] and grad_b[co] as fixed-order sums of the partials: one wave
+// per entry, lane l sums partials l, l + 64, ..., then a fixed shuffle tree.
 template <int CIN, int COUT>
-__global__ void k_wgrad_reduce(const float* __restrict__ partial, int nblocks, float* __restrict__ gw,
-                               float* __restrict__ gb)
+__global__ void __launch_bounds__(kThreads) k_wgrad_reduce(const float* __restrict__ partial, int nblocks,
+                                                           float* __restrict__ gw, float* __restrict__ gb)
 {
     constexpr int K = kdim(CIN), NP = npad16(K + 1), MT = (COUT + 15) / 16;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= COUT * (K + 1)) return;
+    const int i = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= COUT * (K + 1)) return;  // whole waves leave together
     const int co = i / (K + 1), k = i % (K + 1);
     float s = 0.f;
-    for (int g = 0; g < nblocks; ++g) s += partial[((size_t)g * 16 * MT + co) * NP + k];
+    for (int g = lane; g < nblocks; g += 64) s += partial[((size_t)g * 16 * MT + co) * NP + k];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+    if (lane != 0) return;
     if (k < K) gw[(size_t)co * K + k] = s;
     else gb[co] = s;
 }
@@ -548,8 +553,9 @@ void launch_wgrad(const NetWs& ws, const SrcIn& in, const SrcG& g, int l, int ba
     hipLaunchKernelGGL((k_wgrad<CIN, COUT, SrcIn, SrcG>), dim3(nb), dim3(kThreads), 0, s, in, g, ws.partial, H, W,
                        tx, ty, batch);
     const int nred = COUT * (kdim(CIN) + 1);
-    hipLaunchKernelGGL((k_wgrad_reduce<CIN, COUT>), dim3((nred + 255) / 256), dim3(256), 0, s, ws.partial, nb,
-                       grad + param_w_off(l), grad + param_b_off(l));
+    constexpr int per_block = kThreads / 64;
+    hipLaunchKernelGGL((k_wgrad_reduce<CIN, COUT>), dim3((nred + per_block - 1) / per_block), dim3(kThreads), 0, s,
+                       ws.partial, nb, grad + param_w_off(l), grad + param_b_off(l));
 }
 
 hipError_t launch_backward(const NetWs& ws, const float* params, int batch, int H, int W, const float* w,

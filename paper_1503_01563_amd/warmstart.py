@@ -13,7 +13,9 @@ z0 = c x0 + D_rows^T clip(p1, -a_x, a_x).
 
 Command line (runs on a GPU):
   python -m paper_1503_01563_amd.warmstart train --out DIR [--n-train N ...]
-writes DIR/warm_start_params.npy and DIR/warm_start.json.
+  python -m paper_1503_01563_amd.warmstart tune --out DIR   (shipped parameters)
+writes DIR/warm_start_params.npy and DIR/warm_start.json (c chosen on the
+validation grids by time to the exact cut, then the test-grid comparison).
 """
 from __future__ import annotations
 
@@ -153,9 +155,42 @@ def load_params(dev=None):
     return _t(p, dev), float(meta["c"])
 
 
+C_CANDIDATES = (0.0, 0.25, 0.5, 1.0, 2.0)
+
+
+def choose_c(params, n_val, log=print):
+    """Coefficient c of x0 in the warm state with the least total time to the
+    exact cut on the validation grids (network included)."""
+    best = None
+    for c in C_CANDIDATES:
+        rows = compare(params, c, range(VAL_SEED0, VAL_SEED0 + n_val), repeats=3)
+        ci = sum(r["cold_iters"] for r in rows)
+        wi = sum(r["warm_iters"] for r in rows)
+        cm = sum(r["cold_ms"] for r in rows)
+        wm = sum(r["warm_ms"] for r in rows)
+        log("validation c=%.2f: iters cold %d warm %d; ms cold %.1f warm %.1f" % (c, ci, wi, cm, wm))
+        if best is None or (wm, wi) < (best[3], best[1]):
+            best = (c, wi, ci, wm, cm)
+    return best
+
+
+def test_summary(params, c, n_test):
+    rows = compare(params, c, range(TEST_SEED0, TEST_SEED0 + n_test), repeats=3)
+    return rows, {
+        "test": rows,
+        "test_cold_iters": sum(r["cold_iters"] for r in rows),
+        "test_warm_iters": sum(r["warm_iters"] for r in rows),
+        "test_cold_ms_median": float(np.median([r["cold_ms"] for r in rows])),
+        "test_warm_ms_median": float(np.median([r["warm_ms"] for r in rows])),
+        "test_cold_ms_total": float(np.sum([r["cold_ms"] for r in rows])),
+        "test_warm_ms_total": float(np.sum([r["warm_ms"] for r in rows])),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train"])
+    ap.add_argument("cmd", choices=["train", "tune"],
+                    help="train: data, training, c and test; tune: c and test for shipped parameters")
     ap.add_argument("--out", required=True)
     ap.add_argument("--n-train", type=int, default=2000)
     ap.add_argument("--target-iters", type=int, default=400)
@@ -168,38 +203,29 @@ def main():
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     log = lambda m: print(m, flush=True)
-    dev = torch.device("cuda:0")
-    data = build_dataset(range(TRAIN_SEED0, TRAIN_SEED0 + args.n_train), iters=args.target_iters, log=log)
-    params, hist = train(data, steps=args.steps, batch=args.batch, crop=args.crop, lr=args.lr, log=log)
-    del data
-    torch.cuda.empty_cache()
-    best = None
-    for c in (0.0, 0.5, 1.0):
-        rows = compare(params, c, range(VAL_SEED0, VAL_SEED0 + args.n_val), dev=dev)
-        ci = sum(r["cold_iters"] for r in rows)
-        wi = sum(r["warm_iters"] for r in rows)
-        log("validation c=%.1f: cold iters %d, warm iters %d" % (c, ci, wi))
-        if best is None or wi < best[1]:
-            best = (c, wi, ci)
-    c = best[0]
-    rows = compare(params, c, range(TEST_SEED0, TEST_SEED0 + args.n_test), dev=dev, repeats=3)
-    summary = {
-        "c": c, "n_train": args.n_train, "target_iters": args.target_iters, "steps": args.steps,
-        "batch": args.batch, "crop": args.crop, "lr": args.lr, "final_loss": hist[-1][1],
-        "loss_history": hist[::5],
-        "validation": {"c": c, "warm_iters": best[1], "cold_iters": best[2]},
-        "test": rows,
-        "test_cold_iters": sum(r["cold_iters"] for r in rows),
-        "test_warm_iters": sum(r["warm_iters"] for r in rows),
-        "test_cold_ms_median": float(np.median([r["cold_ms"] for r in rows])),
-        "test_warm_ms_median": float(np.median([r["warm_ms"] for r in rows])),
-    }
+    if args.cmd == "train":
+        data = build_dataset(range(TRAIN_SEED0, TRAIN_SEED0 + args.n_train), iters=args.target_iters, log=log)
+        params, hist = train(data, steps=args.steps, batch=args.batch, crop=args.crop, lr=args.lr, log=log)
+        del data
+        torch.cuda.empty_cache()
+        summary = {"n_train": args.n_train, "target_iters": args.target_iters, "steps": args.steps,
+                   "batch": args.batch, "crop": args.crop, "lr": args.lr, "final_loss": hist[-1][1],
+                   "loss_history": hist[::5]}
+    else:
+        params, _ = load_params()
+        summary = {k: v for k, v in json.load(open(META_FILE)).items()
+                   if k not in ("c", "validation") and not k.startswith("test")}
+    c, wi, ci, wm, cm = choose_c(params, args.n_val, log=log)
+    rows, tests = test_summary(params, c, args.n_test)
+    summary.update({"c": c, "validation": {"c": c, "warm_iters": wi, "cold_iters": ci, "warm_ms": wm,
+                                           "cold_ms": cm}})
+    summary.update(tests)
     np.save(os.path.join(args.out, "warm_start_params.npy"), params.cpu().numpy())
     with open(os.path.join(args.out, "warm_start.json"), "w") as f:
         json.dump(summary, f, indent=1)
-    log("test: cold iters %d warm iters %d; median ms cold %.2f warm %.2f" % (
-        summary["test_cold_iters"], summary["test_warm_iters"], summary["test_cold_ms_median"],
-        summary["test_warm_ms_median"]))
+    log("test: c %.2f; iters cold %d warm %d; median ms cold %.2f warm %.2f; total ms cold %.1f warm %.1f" % (
+        c, summary["test_cold_iters"], summary["test_warm_iters"], summary["test_cold_ms_median"],
+        summary["test_warm_ms_median"], summary["test_cold_ms_total"], summary["test_warm_ms_total"]))
 
 
 if __name__ == "__main__":
