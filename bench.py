@@ -11,8 +11,9 @@ steps (voxels x chain families x iterations / wall time).  `roofline` rates the
 chain-sweep kernels (the dominant kernels) by their event-timed launches
 against HBM bandwidth, with 16 algorithmic bytes per voxel-sweep.
 `warm_start` compares the time to the exact cut from a cold start and from
-the trained network's warm start on held-out 512x512 grids (outside the timed
-steps).  `cpu_baseline` times the CPU oracle (FP64, one thread) on a bounded
+the trained network's warm start on held-out 512x512 grids, `dual_reuse` from
+a cold start and from the previous frame's dual over a sequence of edited
+grids (both outside the timed steps).  `cpu_baseline` times the CPU oracle (FP64, one thread) on a bounded
 number of iterations of the same problem, and checks the GPU cut against the
 oracle's max-flow energy.
 """
@@ -189,9 +190,31 @@ def main():
     }
     if args.warm_grids > 0:
         out["warm_start"] = warm_start_section(args.warm_grids)
+        out["dual_reuse"] = dual_reuse_section()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a, last.energy, args.cpu_seconds)
     print(json.dumps(out))
+
+
+def dual_reuse_section(frames=8, shape=(512, 512), frac=0.02):
+    """Time to exact cut over a sequence of related problems (an integer grid
+    with 2 % of its unaries redrawn per frame), cold against reusing the
+    previous frame's dual."""
+    from paper_1503_01563_amd import gen, warmstart
+    rows = warmstart.sequence_compare(gen.edit_sequence(shape, 7000, frames, frac=frac))
+    rows = rows[1:]  # frame 0 has no predecessor
+    return {
+        "workload": "%d frames of a %dx%d integer grid, %.0f%% of the unaries redrawn per frame"
+                    % (frames - 1, shape[0], shape[1], 100 * frac),
+        "cold_ms_total": float(sum(r["cold_ms"] for r in rows)),
+        "warm_ms_total": float(sum(r["warm_ms"] for r in rows)),
+        "cold_iters_total": int(sum(r["cold_iters"] for r in rows)),
+        "warm_iters_total": int(sum(r["warm_iters"] for r in rows)),
+        "all_certified": all(r["cold_ok"] and r["warm_ok"] for r in rows),
+        "same_energy": all(r["cold_energy"] == r["warm_energy"] for r in rows),
+        "note": "warm state from the previous frame's row duals (row prox of its final state), "
+                "re-clipped to the new weights, plus its primal",
+    }
 
 
 def warm_start_section(n_grids):

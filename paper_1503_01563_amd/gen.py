@@ -19,6 +19,10 @@ stand in for them):
                          log-likelihood ratio), a = lam * exp(-dI^2 / (2 0.1^2)),
                          both rounded to multiples of 2^-8.
   * ``batch_sizes``   -- uneven (H, W) pairs for batched solves.
+  * ``ellipse_sequence``, ``edit_sequence`` -- frames of drifting ellipses, and
+                         an integer grid whose unaries are partly redrawn per
+                         frame (related problems for reusing one frame's dual
+                         in the next).
 """
 from __future__ import annotations
 
@@ -55,16 +59,12 @@ def _quantise(x):
     return (np.round(np.asarray(x, np.float64) / DYADIC) * DYADIC).astype(np.float32)
 
 
-def ellipse_image(shape, seed, sigma=0.15, k_range=(3, 8), axes_frac=(0.05, 0.25)):
-    """Noisy two-region image in [D][H][W] or [H][W]: 0.7 inside random ellipses."""
-    rng = _rng(seed)
-    shape = tuple(int(s) for s in shape)
+def _ellipses(rng, shape, k_range=(3, 8), axes_frac=(0.05, 0.25)):
+    """Random ellipses (ellipsoids): list of (centre, semi-axes, rotation)."""
     nd = len(shape)
     k = int(rng.integers(k_range[0], k_range[1] + 1))
-    grids = np.meshgrid(*[np.arange(s, dtype=np.float64) + 0.5 for s in shape], indexing="ij")
-    coords = np.stack([g.ravel() for g in grids], axis=1)  # (n, nd), numpy axis order
-    inside = np.zeros(coords.shape[0], dtype=bool)
     ext = np.array(shape, dtype=np.float64)
+    out = []
     for _ in range(k):
         centre = rng.uniform(0, 1, size=nd) * ext
         if nd == 2:
@@ -76,16 +76,29 @@ def ellipse_image(shape, seed, sigma=0.15, k_range=(3, 8), axes_frac=(0.05, 0.25
             semi = rng.uniform(axes_frac[0], axes_frac[1], size=3) * ext
             q, r = np.linalg.qr(rng.normal(size=(3, 3)))
             rot = q * np.sign(np.diag(r))
+        out.append((centre, semi, rot))
+    return out
+
+
+def _render(shape, ellipses, rng, sigma):
+    grids = np.meshgrid(*[np.arange(s, dtype=np.float64) + 0.5 for s in shape], indexing="ij")
+    coords = np.stack([g.ravel() for g in grids], axis=1)  # (n, nd), numpy axis order
+    inside = np.zeros(coords.shape[0], dtype=bool)
+    for centre, semi, rot in ellipses:
         d = (coords - centre) @ rot
         inside |= np.sum((d / semi) ** 2, axis=1) <= 1.0
     img = np.where(inside, 0.7, 0.3).reshape(shape)
-    img = img + rng.normal(0.0, sigma, size=shape)
-    return img
+    return img + rng.normal(0.0, sigma, size=shape)
 
 
-def ellipse_grid(shape, seed, lam=2.0, sigma=0.15, beta_sigma=0.1):
-    """Segmentation-shaped cut problem from a noisy ellipse (ellipsoid) image."""
-    img = ellipse_image(shape, seed, sigma=sigma)
+def ellipse_image(shape, seed, sigma=0.15, k_range=(3, 8), axes_frac=(0.05, 0.25)):
+    """Noisy two-region image in [D][H][W] or [H][W]: 0.7 inside random ellipses."""
+    rng = _rng(seed)
+    shape = tuple(int(s) for s in shape)
+    return _render(shape, _ellipses(rng, shape, k_range, axes_frac), rng, sigma)
+
+
+def _image_to_grid(img, lam, sigma, beta_sigma):
     w = ((img - 0.7) ** 2 - (img - 0.3) ** 2) / (2.0 * sigma ** 2)
     a = []
     nd = img.ndim
@@ -95,6 +108,44 @@ def ellipse_grid(shape, seed, lam=2.0, sigma=0.15, beta_sigma=0.1):
         aj = lam * np.exp(-((nxt - img) ** 2) / (2.0 * beta_sigma ** 2))
         a.append(_zero_last(_quantise(aj), j))
     return _quantise(w), a
+
+
+def ellipse_grid(shape, seed, lam=2.0, sigma=0.15, beta_sigma=0.1):
+    """Segmentation-shaped cut problem from a noisy ellipse (ellipsoid) image."""
+    return _image_to_grid(ellipse_image(shape, seed, sigma=sigma), lam, sigma, beta_sigma)
+
+
+def edit_sequence(shape, seed, frames, frac=0.02, w_max=20, a_max=10):
+    """Integer grid edited frame by frame (as in interactive segmentation):
+    frame 0 is `iid_grid`, each later frame redraws a fraction `frac` of the
+    unaries of the previous one; the edge weights stay.  Returns a list of (w, a)."""
+    w, a = iid_grid(shape, seed, w_max, a_max)
+    rng = _rng(seed + 1)
+    out = [(w, a)]
+    for _ in range(1, frames):
+        m = rng.random(w.shape) < frac
+        w = w.copy()
+        w[m] = rng.integers(-w_max, w_max + 1, size=int(m.sum())).astype(np.float32)
+        out.append((w, a))
+    return out
+
+
+def ellipse_sequence(shape, seed, frames, speed=2.0, lam=2.0, sigma=0.15, beta_sigma=0.1):
+    """Frames of moving ellipses (a video-like sequence of related cut problems):
+    every ellipse drifts by a random velocity of `speed` pixels per frame; each
+    frame has fresh noise.  Returns a list of (w, a)."""
+    rng = _rng(seed)
+    shape = tuple(int(s) for s in shape)
+    ells = _ellipses(rng, shape)
+    vel = []
+    for _ in ells:
+        ang = rng.uniform(0, 2 * np.pi)
+        vel.append(speed * np.array([np.sin(ang), np.cos(ang)]))
+    out = []
+    for t in range(frames):
+        moved = [(c + t * v, semi, rot) for (c, semi, rot), v in zip(ells, vel)]
+        out.append(_image_to_grid(_render(shape, moved, rng, sigma), lam, sigma, beta_sigma))
+    return out
 
 
 def batch_sizes(count, seed, lo=128, hi=1024):

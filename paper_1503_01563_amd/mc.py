@@ -240,6 +240,8 @@ def tv_prox_chains(v: torch.Tensor, a_axis: torch.Tensor, axis: int, return_p=Fa
     x = x_out if x_out is not None else torch.empty_like(v)
     p = (p_out if p_out is not None else torch.empty_like(v)) if return_p else None
     _dev_f32(x, shape, "x_out")
+    if p is not None:
+        _dev_f32(p, shape, "p_out")
     rc = lib.mc_tv_prox_chains(context(dev), ctypes.byref(_grid(shape)), int(axis), vp, apn,
                                ctypes.c_void_p(x.data_ptr()),
                                ctypes.c_void_p(p.data_ptr()) if p is not None else None,

@@ -111,6 +111,48 @@ def warm_state(params, w, a_x, a_y, c):
     return mc.ws_warm_state(out[0], a_x, c)
 
 
+def dual_reuse_state(z_prev, a_x_prev, x_prev, a_x_new, c=1.0):
+    """Starting state for the next of a sequence of related 2D problems, from
+    the final two-set state of the previous solve -- the paper's warm start
+    by reusing dual vectors (Sec. 4.4, 6.1): the row edge duals of z_prev (the
+    duals of its row prox) re-clipped to the new weights, plus c times the
+    previous primal: z0 = c x_prev + D_rows^T clip(p1_prev, -a_x_new, a_x_new)."""
+    H, W = a_x_new.shape
+    out = torch.empty((2, H, W), dtype=torch.float32, device=a_x_new.device)
+    if x_prev is None:
+        out[0].zero_()
+    else:
+        out[0].copy_(x_prev)
+    scratch = torch.empty((H, W), dtype=torch.float32, device=a_x_new.device)
+    mc.tv_prox_chains(z_prev.view(H, W), a_x_prev, 0, return_p=True, x_out=scratch, p_out=out[1])
+    return mc.ws_warm_state(out, a_x_new, c)
+
+
+def sequence_compare(frames, c=1.0, check_every=2, dev=None):
+    """Cold against dual-reuse solves of consecutive frames [(w, a), ...]:
+    per frame the iterations, times (ms, state construction included) and
+    energies."""
+    dev = dev or torch.device("cuda:0")
+    rows = []
+    prev = None
+    for t, (w, a) in enumerate(frames):
+        tw, ta = _t(w, dev), [_t(a[0], dev), _t(a[1], dev)]
+        cold = timed_solve(tw, ta, None, check_every=check_every)
+        s = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        z0 = None if prev is None else dual_reuse_state(prev[0], prev[1], prev[2], ta[0], c)
+        r = mc.tv_solve(tw, ta, z0=z0, max_iters=3000, check_every=check_every, return_x=True, return_z=True)
+        e1.record(s)
+        e1.synchronize()
+        rows.append({"frame": t, "cold_iters": cold.result.iters, "warm_iters": r.iters,
+                     "cold_ms": cold.ms, "warm_ms": e0.elapsed_time(e1),
+                     "cold_energy": cold.result.energy, "warm_energy": r.energy,
+                     "cold_ok": cold.result.converged, "warm_ok": r.converged})
+        prev = (r.z, ta[0], r.x)
+    return rows
+
+
 @dataclass
 class TimedSolve:
     result: mc.SolveResult
