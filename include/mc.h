@@ -21,6 +21,13 @@
  * (with MC_VALIDATE they must be 0).  Weights must be >= 0 (Sec. 2: the
  * pairwise terms are submodular cut weights).
  *
+ * 8-connected 2D grids (mc_grid.conn = 8).  Four weight arrays: a[0] along
+ * W, a[1] along H as above, a[2][r][c] the diagonal (r,c)-(r+1,c+1) and
+ * a[3][r][c] the anti-diagonal (r+1,c)-(r,c+1) of cell (r, c) (last row and
+ * column ignored).  The diagonal edges are split into two families of
+ * zig-zag chains over pairs of rows (Sec. 3.1, Fig. 1), solved with the
+ * rows and columns in the product space (r = 4).
+ *
  * Memory.  Every array argument is a DEVICE pointer owned by the caller,
  * contiguous, in the grid layout above, float32 unless stated; 256-byte
  * alignment is recommended.  Host-side outputs (mc_stats, energies) are
@@ -68,7 +75,7 @@ typedef struct mc_ctx mc_ctx;
 
 typedef struct {
     int32_t ndim;     /* 2 or 3 */
-    int32_t reserved;
+    int32_t conn;     /* 0 (or 4 / 6): axis edges only; 8: 2D 8-connected (see below) */
     int64_t dims[3];  /* ndim 2: {H, W}; ndim 3: {D, H, W} */
 } mc_grid;
 
@@ -111,10 +118,12 @@ int mc_ctx_destroy(mc_ctx *ctx);
 /*
  * mc_tv_solve -- minimum cut of one grid (Sec. 2-4).
  *   w          [n] unaries.
- *   a          host array of ndim device pointers, a[j] = [n] weights along axis j.
+ *   a          host array of ndim device pointers, a[j] = [n] weights along axis j
+ *              (4 arrays for an 8-connected grid).
  *   z0         nullable warm start of the splitting state (Sec. 4.4: reuse of
  *              the dual vectors); n entries for the two-set form, ndim*n for
- *              the product space (family j at offset j*n).
+ *              the product space (family j at offset j*n), 4*n for an
+ *              8-connected grid (rows, columns, even and odd zig-zag strips).
  *   x_out      nullable [n]: primal TV estimate x = -w - sum_j D_j^T p_j at the last
  *              check, p the edge duals of the chain proxes clipped to [-a, a].
  *   labels_out [n] uint8, 1 = in S.
@@ -144,6 +153,7 @@ int mc_tv_prox_chains(mc_ctx *ctx, const mc_grid *grid, int axis,
 /*
  * mc_cut_energy -- E(S) of eq. (4) in FP64 with a fixed reduction order;
  * exact for integer and dyadic data.  labels [n] uint8 (non-zero = in S).
+ * a holds ndim arrays, or 4 for an 8-connected grid.
  * Synchronises the stream; energy_out is a host pointer.
  */
 int mc_cut_energy(mc_ctx *ctx, const mc_grid *grid, const float *w,

@@ -53,6 +53,9 @@ int make_geo(const mc_grid* grid, Geo* g)
     g->D = (int)D; g->H = (int)H; g->W = (int)W;
     g->n = (int)n;
     g->ndim = grid->ndim;
+    if (grid->conn != 0 && grid->conn != 4 && grid->conn != 6 && grid->conn != 8)
+        return fail(MC_ERR_INVALID_ARG, "conn must be 0, 4, 6 or 8");
+    if (grid->conn == 8 && grid->ndim != 2) return fail(MC_ERR_INVALID_ARG, "8-connected grids are 2D");
     return MC_OK;
 }
 
@@ -136,6 +139,130 @@ int check_ctx(mc_ctx* c)
     return MC_OK;
 }
 
+// 8-connected 2D grids: product-space splitting over rows, columns and the
+// two zig-zag families (Sec. 3.1, 4.3), certified like the other grids.
+int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const float* z0, float* x_out,
+           uint8_t* labels_out, float* z_out, mc_stats* stats, const mc_opts& o, hipStream_t s)
+{
+    constexpr int R = 4;
+    const size_t n = (size_t)g.n;
+    const int H = g.H, W = g.W;
+    const size_t nz = (size_t)2 * (H > 1 ? H - 1 : 0) * W;
+    if (nz > (size_t)INT32_MAX) return fail(MC_ERR_INVALID_ARG, "8-connected grid too large (2(H-1)W > 2^31-1)");
+    int rc;
+    if ((rc = ensure_ws(c, n, R))) return rc;
+    const size_t need = R * n + 4 * nz;
+    if (need > c->g8cap) {
+        (void)hipFree(c->g8buf);
+        c->g8buf = nullptr;
+        c->g8cap = 0;
+        if (hipMalloc(&c->g8buf, sizeof(float) * need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MC_ERR_NOMEM, "8-connected workspace allocation failed");
+        }
+        c->g8cap = need;
+    }
+    float* q = c->g8buf;  // R*n prox outputs
+    float* zzv = q + R * n;
+    float* zza = zzv + nz;
+    float* zzx = zza + nz;
+    float* zzp = zzx + nz;
+    Geo gz;
+    gz.D = 1;
+    gz.H = 2 * (H - 1);
+    gz.W = W;
+    gz.n = (int)nz;
+    gz.ndim = 2;
+
+    if (o.flags & MC_VALIDATE) {
+        MC_HIP(launch_validate8(g, w, a, c->partials, c->dout, s));
+        MC_HIP(hipMemcpyAsync(c->hout, c->dout, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        if (c->hout[1] > 0) return fail(MC_ERR_NONFINITE, "non-finite value in w or a");
+        if (c->hout[0] > 0) return fail(MC_ERR_NEGATIVE_WEIGHT, "negative weight or non-zero weight of a missing edge");
+    }
+    if (z0) MC_HIP(hipMemcpyAsync(c->z, z0, sizeof(float) * R * n, hipMemcpyDeviceToDevice, s));
+    else MC_HIP(hipMemsetAsync(c->z, 0, sizeof(float) * R * n, s));
+    MC_HIP(hipEventRecord(c->ev0, s));
+
+    const float* pj[R] = {c->p, c->p + n, c->p + 2 * n, c->p + 3 * n};
+    SweepTimer tm{c, (o.flags & MC_PROFILE) != 0};
+    float taus[kNumTau];
+    tau_ladder(o.tau0, taus);
+    int it = 0, checks = 0;
+    bool converged = false;
+    double cert = INFINITY, energy = INFINITY, lb = -INFINITY, tvgap = NAN;
+    float tau_used = 0.f;
+    float* zc = c->z;
+    float* zn = c->z2;
+    while (it < o.max_iters) {
+        ++it;
+        const bool check = (it % o.check_every == 0) || it == o.max_iters;
+        if (it == 1 && !z0) {
+            // every prox of the zero state is zero (see mc_tv_solve)
+            if (check) MC_HIP(hipMemsetAsync(c->p, 0, sizeof(float) * R * n, s));
+            MC_HIP(launch_cold_product(g, R, w, zn, s));
+        } else {
+            MC_HIP(tm.begin(s));
+            MC_HIP(launch_drp_sweeps(g, 2, zc, a, q, check ? c->p : nullptr, s));
+            MC_HIP(tm.end(s));
+            MC_HIP(launch_zz_gather(H, W, zc + 2 * n, zc + 3 * n, a[2], a[3], zzv, zza, s));
+            if (nz > 0) {
+                MC_HIP(tm.begin(s));
+                MC_HIP(launch_prox(gz, 0, zzv, zza, zzx, check ? zzp : nullptr, s));
+                MC_HIP(tm.end(s));
+            }
+            MC_HIP(launch_zz_scatter(H, W, zc + 2 * n, zc + 3 * n, zzx, check ? zzp : nullptr, q + 2 * n,
+                                     q + 3 * n, c->p + 2 * n, c->p + 3 * n, s));
+            MC_HIP(launch_combine4(n, zc, q, w, zn, s));
+        }
+        float* zt = zc;
+        zc = zn;
+        zn = zt;
+        if (!check) continue;
+        ++checks;
+        MC_HIP(launch_cert8(g, w, a, pj, o.tau0, c->xt, c->partials, c->dout, s));
+        MC_HIP(hipMemcpyAsync(c->hout, c->dout, kCertValues * sizeof(double), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        MC_HIP(tm.drain());
+        energy = INFINITY;
+        for (int k = 0; k < kNumTau; ++k) {
+            if (c->hout[k] < energy) {
+                energy = c->hout[k];
+                tau_used = taus[k];
+            }
+        }
+        tvgap = c->hout[kNumTau];
+        lb = c->hout[kNumTau + 1];
+        cert = energy - lb;
+        if (!isfinite(cert)) return fail(MC_ERR_NUMERIC, "non-finite certificate (NaN/Inf in the state)");
+        if (cert < o.gap_tol) {
+            converged = true;
+            break;
+        }
+    }
+    MC_HIP(hipEventRecord(c->ev1, s));
+    MC_HIP(launch_labels(g, c->xt, tau_used, labels_out, s));
+    if (x_out) MC_HIP(hipMemcpyAsync(x_out, c->xt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    if (z_out) MC_HIP(hipMemcpyAsync(z_out, zc, sizeof(float) * R * n, hipMemcpyDeviceToDevice, s));
+    MC_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    MC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    stats->status = converged ? MC_OK : MC_NOT_CONVERGED;
+    stats->iters = it;
+    stats->cert_gap = cert;
+    stats->energy = energy;
+    stats->lower_bound = lb;
+    stats->tv_gap = tvgap;
+    stats->tau_used = tau_used;
+    stats->ms = ms;
+    MC_HIP(tm.drain());
+    stats->sweep_ms = tm.ms;
+    stats->sweep_launches = tm.launches;
+    stats->checks = checks;
+    return stats->status;
+}
+
 }  // namespace
 
 extern "C" {
@@ -209,6 +336,7 @@ int mc_ctx_destroy(mc_ctx* c)
     (void)hipFree(c->bbuf);
     (void)hipFree(c->bmeta);
     (void)hipFree(c->nbuf);
+    (void)hipFree(c->g8buf);
     if (c->bstream) (void)hipStreamDestroy(c->bstream);
     delete c;
     return MC_OK;
@@ -237,10 +365,12 @@ int mc_cut_energy(mc_ctx* c, const mc_grid* grid, const float* w, const float* c
     Geo g;
     if ((rc = make_geo(grid, &g))) return rc;
     if (!w || !a || !labels || !energy_out) return fail(MC_ERR_INVALID_ARG, "null argument");
-    for (int j = 0; j < g.ndim; ++j)
+    const int na = grid->conn == 8 ? 4 : g.ndim;
+    for (int j = 0; j < na; ++j)
         if (!a[j]) return fail(MC_ERR_INVALID_ARG, "null weight array");
     hipStream_t s = (hipStream_t)stream;
-    MC_HIP(launch_energy(g, w, a, labels, c->partials, c->dout, s));
+    if (grid->conn == 8) MC_HIP(launch_energy8(g, w, a, labels, c->partials, c->dout, s));
+    else MC_HIP(launch_energy(g, w, a, labels, c->partials, c->dout, s));
     MC_HIP(hipMemcpyAsync(c->hout, c->dout, sizeof(double), hipMemcpyDeviceToHost, s));
     MC_HIP(hipStreamSynchronize(s));
     *energy_out = c->hout[0];
@@ -262,6 +392,15 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     if (opts_in) o = *opts_in; else mc_opts_default(&o);
     if (o.max_iters < 1 || o.check_every < 1) return fail(MC_ERR_INVALID_ARG, "max_iters and check_every must be >= 1");
     if (!(o.tau0 >= 0.f)) return fail(MC_ERR_INVALID_ARG, "tau0 must be >= 0");
+    if (grid->conn == 8) {
+        if (g.ndim != 2) return fail(MC_ERR_INVALID_ARG, "8-connected grids are 2D");
+        if (o.variant == MC_VARIANT_TWO_SET) return fail(MC_ERR_INVALID_ARG, "8-connected grids use the product space");
+        if (o.variant != MC_VARIANT_AUTO && o.variant != MC_VARIANT_PRODUCT)
+            return fail(MC_ERR_INVALID_ARG, "unknown variant");
+        for (int j = 2; j < 4; ++j)
+            if (!a[j]) return fail(MC_ERR_INVALID_ARG, "null weight array");
+        return solve8(c, g, w, a, z0, x_out, labels_out, z_out, stats, o, (hipStream_t)stream);
+    }
     bool two_set;
     if (o.variant == MC_VARIANT_AUTO) two_set = g.ndim == 2;
     else if (o.variant == MC_VARIANT_TWO_SET) two_set = true;

@@ -173,6 +173,8 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
     size_t n_total = 0, floats = 0;
     for (int gi = 0; gi < n_grids; ++gi) {
         const mc_grid& gr = grids[gi];
+        if (gr.conn != 0 && gr.conn != 4)
+            return set_error(MC_ERR_INVALID_ARG, "batched grids are 4-connected");
         if (gr.ndim != 2 || gr.dims[0] <= 0 || gr.dims[1] <= 0)
             return set_error(MC_ERR_INVALID_ARG, "batched grids must be 2D with positive dims");
         if (gr.dims[0] * gr.dims[1] > INT32_MAX || gr.dims[0] >= (1 << 30) || gr.dims[1] >= (1 << 30))

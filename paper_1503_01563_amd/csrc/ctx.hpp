@@ -33,6 +33,10 @@ struct mc_ctx {
     char* bmeta = nullptr;           // table, maps, partials, counters
     std::map<unsigned long long, int> tuned_items;  // batch signature -> work items per launch
 
+    // 8-connected grids: prox outputs of the four families, straightened zig-zag chains
+    size_t g8cap = 0;       // floats in g8buf
+    float* g8buf = nullptr;
+
     // warm-start network
     size_t ncap = 0;        // bytes in nbuf
     char* nbuf = nullptr;   // packed weights, activations, gradients, partials

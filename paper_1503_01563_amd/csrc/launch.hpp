@@ -84,6 +84,26 @@ hipError_t launch_drp_final(const Geo& g, int r, const float* z, float* znew, co
 // zn_j = -(w * (1/r)) for j < r.
 hipError_t launch_cold_product(const Geo& g, int r, const float* w, float* zn, hipStream_t s);
 
+// ---- 8-connected 2D grids (a[0..3]: along W, along H, diagonal, anti-diagonal) ----
+
+// Zig-zag families 2 and 3 straightened into chains [2(H-1)][W] (values from
+// z2 / z3, edge weights from the diagonal / anti-diagonal arrays).
+hipError_t launch_zz_gather(int H, int W, const float* z2, const float* z3, const float* add, const float* aad,
+                            float* zv, float* za, hipStream_t s);
+// Back: q2 / q3 per vertex (identity off the family's paths); when zp is not
+// null, the diagonal and anti-diagonal duals per cell.
+hipError_t launch_zz_scatter(int H, int W, const float* z2, const float* z3, const float* zx, const float* zp,
+                             float* q2, float* q3, float* pdd, float* pad, hipStream_t s);
+// Product-space averaging over four families: zn_j = y_j - (2Y - Z + w)/4.
+hipError_t launch_combine4(size_t n, const float* z, const float* q, const float* w, float* zn, hipStream_t s);
+// Certificate, energy and input checks with the diagonal edges.
+hipError_t launch_cert8(const Geo& g, const float* w, const float* const* a, const float* const* p, float tau0,
+                        float* xc, double* partials, double* out, hipStream_t s);
+hipError_t launch_energy8(const Geo& g, const float* w, const float* const* a, const uint8_t* labels,
+                          double* partials, double* out, hipStream_t s);
+hipError_t launch_validate8(const Geo& g, const float* w, const float* const* a, double* partials, double* out,
+                            hipStream_t s);
+
 // Certificate from the edge duals p: primal xc = -w - sum_j D_j^T p_j (FP32
 // out), then out[kCertValues] = {E(S_t) for the ladder, TV gap, LB} in FP64.
 // partials needs kCertValues * kReduceBlocks doubles.

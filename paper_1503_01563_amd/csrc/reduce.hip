@@ -171,6 +171,131 @@ k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, P
     block_reduce_store<kNumTau + 1>(e, partials + (size_t)blockIdx.x * (kNumTau + 1));
 }
 
+// ---- 8-connected 2D grids -------------------------------------------------------
+//
+// a[0..3] weigh the edges (r,c)-(r,c+1), (r,c)-(r+1,c), the diagonal
+// (r,c)-(r+1,c+1) and the anti-diagonal (r+1,c)-(r,c+1), stored at vertex /
+// cell (r,c) and zero where the edge does not exist; p[0..3] are the clipped
+// duals of the same edges (p_e for the chain difference x_v - x_u, u the
+// edge's left end).
+
+struct Ptr4 {
+    const float* p[4];
+};
+
+__device__ __forceinline__ double primal8_voxel(const Geo& g, const float* __restrict__ w, const Ptr4& p,
+                                                float* __restrict__ xc, int i)
+{
+    const int W = g.W, r = i / W, c = i - r * W;
+    // left end of its own row, column and diagonal edges
+    double y = -(double)p.p[0][i] - (double)p.p[1][i] - (double)p.p[2][i];
+    if (c > 0) y += (double)p.p[0][i - 1];
+    if (r > 0) y += (double)p.p[1][i - W];
+    if (r > 0 && c > 0) y += (double)p.p[2][i - W - 1];  // right end of the diagonal of cell (r-1, c-1)
+    if (r > 0) y -= (double)p.p[3][i - W];               // left end (r'+1, c') of cell (r-1, c)
+    if (c > 0) y += (double)p.p[3][i - 1];               // right end (r', c'+1) of cell (r, c-1)
+    const double s = y + (double)w[i];
+    xc[i] = (float)(-s);
+    return s < 0.0 ? s : 0.0;
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_primal8(Geo g, const float* __restrict__ w, Ptr4 p, float* __restrict__ xc, double* __restrict__ partials)
+{
+    double lb = 0.0;
+    const int stride = gridDim.x * kReduceThreads;
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride)
+        lb += primal8_voxel(g, w, p, xc, i);
+    double v[1] = {lb};
+    block_reduce_store<1>(v, partials + blockIdx.x);
+}
+
+// one edge u-v of weight ae and dual pe: ladder energies and TV-gap term
+__device__ __forceinline__ void cut_edge(float xu, int cu, float xv, double ae, double pe, const Taus& tz,
+                                         const float* __restrict__ xc, int v, double (&e)[kNumTau + 1])
+{
+    (void)xv;
+    const float xn = xc[v];
+    const int cn = ladder_count(xn, tz);
+    const int lo = cu < cn ? cu : cn, hi = cu < cn ? cn : cu;
+#pragma unroll
+    for (int t = 0; t < kNumTau; ++t)
+        if (t >= lo && t < hi) e[t] += ae;
+    const double dx = (double)xn - (double)xu;
+    e[kNumTau] += ae * fabs(dx) - pe * dx;
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_cut_ladder8(Geo g, const float* __restrict__ xc, const float* __restrict__ w, Ptr4 a, Ptr4 p, Taus tz,
+              double* __restrict__ partials)
+{
+    double e[kNumTau + 1];
+#pragma unroll
+    for (int t = 0; t <= kNumTau; ++t) e[t] = 0.0;
+    const int stride = gridDim.x * kReduceThreads;
+    const int W = g.W, H = g.H;
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
+        const int r = i / W, c = i - r * W;
+        const float xi = xc[i];
+        const int ci = ladder_count(xi, tz);
+        const double wi = (double)w[i];
+#pragma unroll
+        for (int t = 0; t < kNumTau; ++t)
+            if (t >= ci) e[t] += wi;
+        if (c + 1 < W) cut_edge(xi, ci, 0.f, (double)a.p[0][i], (double)p.p[0][i], tz, xc, i + 1, e);
+        if (r + 1 < H) cut_edge(xi, ci, 0.f, (double)a.p[1][i], (double)p.p[1][i], tz, xc, i + W, e);
+        if (r + 1 < H && c + 1 < W) {
+            cut_edge(xi, ci, 0.f, (double)a.p[2][i], (double)p.p[2][i], tz, xc, i + W + 1, e);
+            // anti-diagonal of cell (r, c): from (r+1, c) to (r, c+1)
+            const float xu = xc[i + W];
+            cut_edge(xu, ladder_count(xu, tz), 0.f, (double)a.p[3][i], (double)p.p[3][i], tz, xc, i + 1, e);
+        }
+    }
+    block_reduce_store<kNumTau + 1>(e, partials + (size_t)blockIdx.x * (kNumTau + 1));
+}
+
+__global__ void __launch_bounds__(kReduceThreads)
+k_energy8(Geo g, const float* __restrict__ w, Ptr4 a, const uint8_t* __restrict__ lab, double* __restrict__ partials)
+{
+    double e = 0.0;
+    const int stride = gridDim.x * kReduceThreads;
+    const int W = g.W, H = g.H;
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
+        const int r = i / W, c = i - r * W;
+        const bool b = lab[i] != 0;
+        if (b) e += (double)w[i];
+        if (c + 1 < W && b != (lab[i + 1] != 0)) e += (double)a.p[0][i];
+        if (r + 1 < H && b != (lab[i + W] != 0)) e += (double)a.p[1][i];
+        if (r + 1 < H && c + 1 < W) {
+            if (b != (lab[i + W + 1] != 0)) e += (double)a.p[2][i];
+            if ((lab[i + W] != 0) != (lab[i + 1] != 0)) e += (double)a.p[3][i];
+        }
+    }
+    double v[1] = {e};
+    block_reduce_store<1>(v, partials + blockIdx.x);
+}
+
+// out[0]: negative weights or non-zero weights of missing edges, out[1]: non-finite values
+__global__ void __launch_bounds__(kReduceThreads)
+k_validate8(Geo g, const float* __restrict__ w, Ptr4 a, double* __restrict__ partials)
+{
+    double bad = 0.0, nonfinite = 0.0;
+    const int stride = gridDim.x * kReduceThreads;
+    const int W = g.W, H = g.H;
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
+        const int r = i / W, c = i - r * W;
+        if (!isfinite(w[i])) nonfinite += 1.0;
+        const bool exists[4] = {c + 1 < W, r + 1 < H, r + 1 < H && c + 1 < W, r + 1 < H && c + 1 < W};
+        for (int j = 0; j < 4; ++j) {
+            const float v = a.p[j][i];
+            if (!isfinite(v)) nonfinite += 1.0;
+            else if (v < 0.f || (!exists[j] && v != 0.f)) bad += 1.0;
+        }
+    }
+    double v[2] = {bad, nonfinite};
+    block_reduce_store<2>(v, partials + 2 * blockIdx.x);
+}
+
 // ---- batched: every reduction block belongs to one grid ------------------------
 
 __device__ __forceinline__ Ptr3 batch_duals(const BatchGrid& t)
@@ -376,6 +501,48 @@ hipError_t launch_cert(const Geo& g, const float* w, const float* const* a,
                        out);
     hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, part_lb, nb,
                        out + kNumTau + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_cert8(const Geo& g, const float* w, const float* const* a, const float* const* p, float tau0,
+                        float* xc, double* partials, double* out, hipStream_t s)
+{
+    Ptr4 pa, pp;
+    for (int j = 0; j < 4; ++j) {
+        pa.p[j] = a[j];
+        pp.p[j] = p[j];
+    }
+    Taus tz;
+    tau_ladder(tau0, tz.t);
+    const int nb = reduce_blocks(g.n);
+    double* part_cut = partials;
+    double* part_lb = partials + (size_t)nb * (kNumTau + 1);
+    hipLaunchKernelGGL(k_primal8, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pp, xc, part_lb);
+    hipLaunchKernelGGL(k_cut_ladder8, dim3(nb), dim3(kReduceThreads), 0, s, g, xc, w, pa, pp, tz, part_cut);
+    hipLaunchKernelGGL(k_finalize<kNumTau + 1>, dim3(1), dim3(kReduceThreads), 0, s, part_cut, nb, out);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, part_lb, nb, out + kNumTau + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy8(const Geo& g, const float* w, const float* const* a, const uint8_t* labels,
+                          double* partials, double* out, hipStream_t s)
+{
+    Ptr4 pa;
+    for (int j = 0; j < 4; ++j) pa.p[j] = a[j];
+    const int nb = reduce_blocks(g.n);
+    hipLaunchKernelGGL(k_energy8, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pa, labels, partials);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate8(const Geo& g, const float* w, const float* const* a, double* partials, double* out,
+                            hipStream_t s)
+{
+    Ptr4 pa;
+    for (int j = 0; j < 4; ++j) pa.p[j] = a[j];
+    const int nb = reduce_blocks(g.n);
+    hipLaunchKernelGGL(k_validate8, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pa, partials);
+    hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kReduceThreads), 0, s, partials, nb, out);
     return hipGetLastError();
 }
 

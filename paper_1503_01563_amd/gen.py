@@ -115,6 +115,21 @@ def ellipse_grid(shape, seed, lam=2.0, sigma=0.15, beta_sigma=0.1):
     return _image_to_grid(ellipse_image(shape, seed, sigma=sigma), lam, sigma, beta_sigma)
 
 
+def ellipse_grid8(shape, seed, lam=2.0, sigma=0.15, beta_sigma=0.1):
+    """8-connected version of `ellipse_grid` (2D): the same image, unaries and
+    axis weights, plus diagonal weights lam / sqrt(2) * exp(-dI^2 / (2 0.1^2))
+    across each cell's diagonal (r,c)-(r+1,c+1) and anti-diagonal
+    (r+1,c)-(r,c+1), stored at (r, c); last row and column zero."""
+    img = ellipse_image(shape, seed, sigma=sigma)
+    w, a = _image_to_grid(img, lam, sigma, beta_sigma)
+    ld = lam / np.sqrt(2.0)
+    dd = np.zeros_like(img)
+    ad = np.zeros_like(img)
+    dd[:-1, :-1] = ld * np.exp(-((img[1:, 1:] - img[:-1, :-1]) ** 2) / (2.0 * beta_sigma ** 2))
+    ad[:-1, :-1] = ld * np.exp(-((img[:-1, 1:] - img[1:, :-1]) ** 2) / (2.0 * beta_sigma ** 2))
+    return w, a + [_quantise(dd), _quantise(ad)]
+
+
 def edit_sequence(shape, seed, frames, frac=0.02, w_max=20, a_max=10):
     """Integer grid edited frame by frame (as in interactive segmentation):
     frame 0 is `iid_grid`, each later frame redraws a fraction `frac` of the

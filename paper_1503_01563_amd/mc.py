@@ -7,7 +7,8 @@ libmc.so is missing or cannot be loaded, every call raises.
 
 Arrays are torch tensors on a ROCm device: ``w`` of the grid shape (H, W) or
 (D, H, W), float32, contiguous; ``a`` a sequence with one tensor of the same
-shape per axis (axis 0 = W, 1 = H, 2 = D).
+shape per axis (axis 0 = W, 1 = H, 2 = D), or four for an 8-connected 2D grid
+(W, H, diagonal, anti-diagonal; see include/mc.h).
 """
 from __future__ import annotations
 
@@ -36,7 +37,7 @@ class McError(RuntimeError):
 
 
 class Grid(ctypes.Structure):
-    _fields_ = [("ndim", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    _fields_ = [("ndim", ctypes.c_int32), ("conn", ctypes.c_int32),
                 ("dims", ctypes.c_int64 * 3)]
 
 
@@ -126,14 +127,22 @@ def context(device: int):
     return _ctx[key]
 
 
-def _grid(shape):
+def _grid(shape, conn=0):
     g = Grid()
     g.ndim = len(shape)
+    g.conn = int(conn)
     if g.ndim not in (2, 3):
         raise ValueError("grid must be 2D or 3D")
     for k, s in enumerate(shape):
         g.dims[k] = int(s)
     return g
+
+
+def _conn_of(a, nd):
+    """8-connected when a 2D grid comes with four weight arrays."""
+    if nd == 2 and len(a) == 4:
+        return 8
+    return 0
 
 
 def _dev_f32(t, shape, name):
@@ -151,10 +160,11 @@ def _stream(device):
 
 
 def _aptrs(a, shape, nd):
-    if len(a) != nd:
-        raise ValueError("need one weight array per axis")
-    return (ctypes.c_void_p * 3)(*([_dev_f32(a[j], shape, "a[%d]" % j).value for j in range(nd)]
-                                   + [None] * (3 - nd)))
+    k = len(a)
+    if k != nd and not (nd == 2 and k == 4):
+        raise ValueError("need one weight array per axis (four for an 8-connected 2D grid)")
+    return (ctypes.c_void_p * 4)(*([_dev_f32(a[j], shape, "a[%d]" % j).value for j in range(k)]
+                                   + [None] * (4 - k)))
 
 
 @dataclass
@@ -203,8 +213,9 @@ def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tens
     dev = w.device.index if w.device.index is not None else torch.cuda.current_device()
     wp = _dev_f32(w, shape, "w")
     ap = _aptrs(a, shape, nd)
-    two_set = (variant == VARIANT_TWO_SET) or (variant == VARIANT_AUTO and nd == 2)
-    nz = w.numel() if two_set else nd * w.numel()
+    conn = _conn_of(a, nd)
+    two_set = conn != 8 and ((variant == VARIANT_TWO_SET) or (variant == VARIANT_AUTO and nd == 2))
+    nz = w.numel() if two_set else (4 if conn == 8 else nd) * w.numel()
     z0p = None
     if z0 is not None:
         if z0.device != w.device or z0.dtype != torch.float32 or not z0.is_contiguous() or z0.numel() != nz:
@@ -217,7 +228,7 @@ def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tens
     z = torch.empty(nz, dtype=torch.float32, device=w.device) if return_z else None
     st = Stats()
     o = make_opts(max_iters, check_every, gap_tol, variant, tau0, validate, profile)
-    rc = lib.mc_tv_solve(context(dev), ctypes.byref(_grid(shape)), wp,
+    rc = lib.mc_tv_solve(context(dev), ctypes.byref(_grid(shape, conn)), wp,
                          ctypes.cast(ap, ctypes.c_void_p), z0p,
                          ctypes.c_void_p(x.data_ptr()) if x is not None else None,
                          ctypes.c_void_p(labels.data_ptr()),
@@ -261,7 +272,7 @@ def cut_energy(w: torch.Tensor, a: Sequence[torch.Tensor], labels: torch.Tensor)
     if labels.dtype != torch.uint8 or tuple(labels.shape) != shape or not labels.is_contiguous():
         raise ValueError("labels must be contiguous uint8 of the grid shape")
     e = ctypes.c_double(0)
-    rc = lib.mc_cut_energy(context(dev), ctypes.byref(_grid(shape)), wp,
+    rc = lib.mc_cut_energy(context(dev), ctypes.byref(_grid(shape, _conn_of(a, nd))), wp,
                            ctypes.cast(ap, ctypes.c_void_p), ctypes.c_void_p(labels.data_ptr()),
                            ctypes.byref(e), _stream(dev))
     _check(rc)

@@ -1,0 +1,89 @@
+"""GPU parity of 8-connected grids (rows, columns and two zig-zag chain
+families in the product space) against the 8-connected reference."""
+import numpy as np
+import pytest
+
+from oracle import grid8
+
+pytestmark = pytest.mark.gpu
+REL_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_01563_amd import mc
+    mc.load_library()
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+
+
+def problem(shape, seed, w_max=20, a_max=10):
+    rng = np.random.default_rng(seed)
+    w = rng.integers(-w_max, w_max + 1, size=shape).astype(np.float32)
+    a = [rng.integers(0, a_max + 1, size=shape).astype(np.float32) for _ in range(4)]
+    a[0][:, -1] = 0
+    a[1][-1, :] = 0
+    for k in (2, 3):
+        a[k][-1, :] = 0
+        a[k][:, -1] = 0
+    return w, a
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (16, 16), (33, 20), (1, 9), (9, 1), (2, 2)])
+def test_cut_energy_bit_exact(dev, shape):
+    from paper_1503_01563_amd import mc
+    import torch
+    w, a = problem(shape, 11)
+    lab = np.random.default_rng(12).integers(0, 2, size=shape).astype(np.uint8)
+    e = mc.cut_energy(T(w, dev), [T(x, dev) for x in a], torch.from_numpy(lab).to(dev))
+    assert e == grid8.cut_energy(w, a, lab)
+
+
+@pytest.mark.parametrize("iters", [1, 2, 5])
+@pytest.mark.parametrize("shape", [(12, 17), (7, 40)])
+def test_iterates_match_reference(dev, shape, iters):
+    """Primal of the certificate after a fixed number of iterations."""
+    from paper_1503_01563_amd import mc
+    w, a = problem(shape, 13)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=iters, check_every=iters, gap_tol=0.0)
+    ref = grid8.dr_solve(w, a, max_iters=iters, gap_tol=0.0, check_every=iters)
+    x = res.x.cpu().numpy()
+    scale = max(1.0, np.abs(ref["x"]).max())
+    assert np.abs(x - ref["x"]).max() / scale <= REL_TOL
+    assert abs(res.lower_bound - ref["lower_bound"]) <= 1e-3 * max(1.0, abs(ref["lower_bound"]))
+
+
+@pytest.mark.parametrize("shape,seed", [((24, 31), 14), ((64, 64), 15), ((3, 50), 16), ((50, 3), 17)])
+def test_solve_exact_against_maxflow(dev, shape, seed):
+    from paper_1503_01563_amd import mc
+    w, a = problem(shape, seed)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=3000, check_every=2, gap_tol=1e-3,
+                      validate=True)
+    assert res.converged
+    e_star, _ = grid8.mincut(w, a)
+    assert res.energy == e_star
+    assert grid8.cut_energy(w, a, res.labels.cpu().numpy()) == e_star
+
+
+def test_image_8connected_exact(dev):
+    """256x256 noisy ellipses with diagonal contrast weights (lambda / sqrt 2)."""
+    from paper_1503_01563_amd import gen, mc
+    w, a = gen.ellipse_grid8((256, 256), 2100)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=3000, check_every=4, gap_tol=1e-3)
+    assert res.converged
+    assert res.energy == grid8.mincut(w, a)[0]
+    print("image 256x256 8-connected: %d iterations, %.1f ms" % (res.iters, res.ms))
+
+
+def test_grid8_rejects_two_set_and_batched(dev):
+    from paper_1503_01563_amd import mc
+    w, a = problem((8, 8), 18)
+    with pytest.raises(mc.McError):
+        mc.tv_solve(T(w, dev), [T(x, dev) for x in a], variant=mc.VARIANT_TWO_SET)
