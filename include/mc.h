@@ -70,6 +70,12 @@ extern "C" {
 #define MC_VARIANT_AUTO 0        /* two-set form for 2D, product space for 3D */
 #define MC_VARIANT_TWO_SET 1     /* r = 2 special case (Sec. 3.3), 2D only */
 #define MC_VARIANT_PRODUCT 2     /* product-space form (Sec. 3.3, eq. (dualA)) */
+/* Other outer iterations over the same chain proxes (4- and 6-connected grids;
+ * state z0 / z_out: r*n floats, the dual blocks y_j (BCD, FISTA) or the point
+ * projected onto K (AP)): */
+#define MC_VARIANT_BCD 3         /* cyclic projections / block coordinate descent (Sec. 4.1) */
+#define MC_VARIANT_AP 4          /* alternating projections in the product space (Sec. 4.2) */
+#define MC_VARIANT_FISTA 5       /* FISTA on the smooth dual, step 1/r (Sec. 4.1) */
 
 typedef struct mc_ctx mc_ctx;
 

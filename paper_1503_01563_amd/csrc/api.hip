@@ -139,6 +139,175 @@ int check_ctx(mc_ctx* c)
     return MC_OK;
 }
 
+// ---- shared by the solve loops ----------------------------------------------------
+
+struct CheckState {
+    double cert = INFINITY, energy = INFINITY, lb = -INFINITY, tvgap = NAN;
+    float tau_used = 0.f;
+    int checks = 0;
+};
+
+// Certificate from the edge duals pj (Sec. 2.2): energies of the threshold
+// ladder, LB, TV gap; `done` when cert < gap_tol.  Synchronises the stream.
+int run_check(mc_ctx* c, const Geo& g, bool conn8, const float* w, const float* const* a, const float* const* pj,
+              const mc_opts& o, const float* taus, SweepTimer& tm, hipStream_t s, CheckState& st, bool& done)
+{
+    ++st.checks;
+    if (conn8) MC_HIP(launch_cert8(g, w, a, pj, o.tau0, c->xt, c->partials, c->dout, s));
+    else MC_HIP(launch_cert(g, w, a, pj, o.tau0, c->xt, c->partials, c->dout, s));
+    MC_HIP(hipMemcpyAsync(c->hout, c->dout, kCertValues * sizeof(double), hipMemcpyDeviceToHost, s));
+    MC_HIP(hipStreamSynchronize(s));
+    MC_HIP(tm.drain());
+    st.energy = INFINITY;
+    for (int k = 0; k < kNumTau; ++k) {
+        if (c->hout[k] < st.energy) {
+            st.energy = c->hout[k];
+            st.tau_used = taus[k];
+        }
+    }
+    st.tvgap = c->hout[kNumTau];
+    st.lb = c->hout[kNumTau + 1];
+    st.cert = st.energy - st.lb;
+    if (!isfinite(st.cert)) return fail(MC_ERR_NUMERIC, "non-finite certificate (NaN/Inf in the state)");
+    done = st.cert < o.gap_tol;
+    return MC_OK;
+}
+
+// Labels of the last certificate's primal, optional outputs, stats.
+int finish_solve(mc_ctx* c, const Geo& g, const float* state, size_t nstate, float* x_out, uint8_t* labels_out,
+                 float* z_out, mc_stats* stats, int it, bool converged, const CheckState& st, SweepTimer& tm,
+                 hipStream_t s)
+{
+    const size_t n = (size_t)g.n;
+    MC_HIP(hipEventRecord(c->ev1, s));
+    MC_HIP(launch_labels(g, c->xt, st.tau_used, labels_out, s));
+    if (x_out) MC_HIP(hipMemcpyAsync(x_out, c->xt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    if (z_out) MC_HIP(hipMemcpyAsync(z_out, state, sizeof(float) * nstate, hipMemcpyDeviceToDevice, s));
+    MC_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    MC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    stats->status = converged ? MC_OK : MC_NOT_CONVERGED;
+    stats->iters = it;
+    stats->cert_gap = st.cert;
+    stats->energy = st.energy;
+    stats->lower_bound = st.lb;
+    stats->tv_gap = st.tvgap;
+    stats->tau_used = st.tau_used;
+    stats->ms = ms;
+    MC_HIP(tm.drain());
+    stats->sweep_ms = tm.ms;
+    stats->sweep_launches = tm.launches;
+    stats->checks = st.checks;
+    return stats->status;
+}
+
+// Cyclic projections (BCD), alternating projections in the product space and
+// FISTA on the dual (Sec. 4.1-4.2) over the same chain proxes; 4- and
+// 6-connected grids.  State (z0 / z_out): the dual blocks y (BCD, FISTA) or
+// the point l projected onto K (AP), r*n floats.
+int solve_variant(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const float* z0, float* x_out,
+                  uint8_t* labels_out, float* z_out, mc_stats* stats, const mc_opts& o, hipStream_t s)
+{
+    const int r = g.ndim;
+    const size_t n = (size_t)g.n;
+    int rc;
+    if ((rc = ensure_ws(c, n, r))) return rc;
+    // buffers: A (r n), B (r n), V (r n), X (n)
+    const size_t need = 3 * (size_t)r * n + n;
+    if (need > c->vcap) {
+        (void)hipFree(c->vbuf);
+        c->vbuf = nullptr;
+        c->vcap = 0;
+        if (hipMalloc(&c->vbuf, sizeof(float) * need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MC_ERR_NOMEM, "variant workspace allocation failed");
+        }
+        c->vcap = need;
+    }
+    float* A = c->vbuf;
+    float* B = A + r * n;
+    float* V = B + r * n;
+    float* X = V + r * n;
+    if (o.flags & MC_VALIDATE) {
+        MC_HIP(launch_validate(g, w, a, c->partials, c->dout, s));
+        MC_HIP(hipMemcpyAsync(c->hout, c->dout, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        if (c->hout[1] > 0) return fail(MC_ERR_NONFINITE, "non-finite value in w or a");
+        if (c->hout[0] > 0) return fail(MC_ERR_NEGATIVE_WEIGHT, "negative weight or non-zero weight on a last slice");
+    }
+    if (z0) MC_HIP(hipMemcpyAsync(A, z0, sizeof(float) * r * n, hipMemcpyDeviceToDevice, s));
+    else MC_HIP(hipMemsetAsync(A, 0, sizeof(float) * r * n, s));
+    if (o.variant == MC_VARIANT_FISTA) MC_HIP(hipMemcpyAsync(B, A, sizeof(float) * r * n, hipMemcpyDeviceToDevice, s));
+    if (o.variant == MC_VARIANT_BCD) {
+        // x = u - sum_j y_j
+        MC_HIP(launch_neg(n, w, X, s));
+        for (int j = 0; j < r; ++j) MC_HIP(launch_sub(n, A + (size_t)j * n, X, s));
+    }
+    MC_HIP(hipEventRecord(c->ev0, s));
+
+    const float* pj[3] = {c->p, c->p + n, c->p + 2 * n};
+    SweepTimer tm{c, (o.flags & MC_PROFILE) != 0};
+    float taus[kNumTau];
+    tau_ladder(o.tau0, taus);
+    CheckState st;
+    int it = 0;
+    bool converged = false;
+    double t = 1.0;
+    float* y = A;   // FISTA: current y, B: previous
+    float* yp = B;
+    while (it < o.max_iters) {
+        ++it;
+        const bool check = (it % o.check_every == 0) || it == o.max_iters;
+        if (o.variant == MC_VARIANT_BCD) {
+            for (int i = 0; i < r; ++i) {
+                float* yi = A + (size_t)i * n;
+                MC_HIP(launch_add(n, X, yi, V, s));
+                MC_HIP(tm.begin(s));
+                MC_HIP(launch_prox(g, i, V, a[i], X, check ? c->p + (size_t)i * n : nullptr, s));
+                MC_HIP(tm.end(s));
+                MC_HIP(launch_diff(n, V, X, yi, s));
+            }
+        } else if (o.variant == MC_VARIANT_AP) {
+            const bool cold = it == 1 && !z0;
+            if (cold) {
+                if (check) MC_HIP(hipMemsetAsync(c->p, 0, sizeof(float) * r * n, s));
+            } else {
+                for (int j = 0; j < r; ++j) {
+                    MC_HIP(tm.begin(s));
+                    MC_HIP(launch_prox(g, j, A + (size_t)j * n, a[j], V + (size_t)j * n,
+                                       check ? c->p + (size_t)j * n : nullptr, s));
+                    MC_HIP(tm.end(s));
+                }
+            }
+            MC_HIP(launch_ap_update(n, r, A, V, w, cold, s));
+        } else {  // FISTA
+            const double t_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t * t));
+            const float beta = (float)((t - 1.0) / t_next);
+            t = t_next;
+            MC_HIP(launch_fista_pre(n, r, y, yp, beta, w, V, s));
+            for (int j = 0; j < r; ++j) {
+                MC_HIP(tm.begin(s));
+                MC_HIP(launch_prox(g, j, V + (size_t)j * n, a[j], yp + (size_t)j * n,
+                                   check ? c->p + (size_t)j * n : nullptr, s));
+                MC_HIP(tm.end(s));
+            }
+            MC_HIP(launch_rsub((size_t)r * n, V, yp, s));  // new y = v - prox(v), into the old buffer
+            float* tmp = y;
+            y = yp;
+            yp = tmp;
+        }
+        if (!check) continue;
+        bool done = false;
+        if ((rc = run_check(c, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
+        if (done) {
+            converged = true;
+            break;
+        }
+    }
+    const float* state = o.variant == MC_VARIANT_FISTA ? y : A;
+    return finish_solve(c, g, state, (size_t)r * n, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
+}
+
 // 8-connected 2D grids: product-space splitting over rows, columns and the
 // two zig-zag families (Sec. 3.1, 4.3), certified like the other grids.
 int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const float* z0, float* x_out,
@@ -189,10 +358,9 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
     SweepTimer tm{c, (o.flags & MC_PROFILE) != 0};
     float taus[kNumTau];
     tau_ladder(o.tau0, taus);
-    int it = 0, checks = 0;
+    CheckState st;
+    int it = 0;
     bool converged = false;
-    double cert = INFINITY, energy = INFINITY, lb = -INFINITY, tvgap = NAN;
-    float tau_used = 0.f;
     float* zc = c->z;
     float* zn = c->z2;
     while (it < o.max_iters) {
@@ -220,47 +388,14 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
         zc = zn;
         zn = zt;
         if (!check) continue;
-        ++checks;
-        MC_HIP(launch_cert8(g, w, a, pj, o.tau0, c->xt, c->partials, c->dout, s));
-        MC_HIP(hipMemcpyAsync(c->hout, c->dout, kCertValues * sizeof(double), hipMemcpyDeviceToHost, s));
-        MC_HIP(hipStreamSynchronize(s));
-        MC_HIP(tm.drain());
-        energy = INFINITY;
-        for (int k = 0; k < kNumTau; ++k) {
-            if (c->hout[k] < energy) {
-                energy = c->hout[k];
-                tau_used = taus[k];
-            }
-        }
-        tvgap = c->hout[kNumTau];
-        lb = c->hout[kNumTau + 1];
-        cert = energy - lb;
-        if (!isfinite(cert)) return fail(MC_ERR_NUMERIC, "non-finite certificate (NaN/Inf in the state)");
-        if (cert < o.gap_tol) {
+        bool done = false;
+        if ((rc = run_check(c, g, true, w, a, pj, o, taus, tm, s, st, done))) return rc;
+        if (done) {
             converged = true;
             break;
         }
     }
-    MC_HIP(hipEventRecord(c->ev1, s));
-    MC_HIP(launch_labels(g, c->xt, tau_used, labels_out, s));
-    if (x_out) MC_HIP(hipMemcpyAsync(x_out, c->xt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
-    if (z_out) MC_HIP(hipMemcpyAsync(z_out, zc, sizeof(float) * R * n, hipMemcpyDeviceToDevice, s));
-    MC_HIP(hipStreamSynchronize(s));
-    float ms = 0.f;
-    MC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    stats->status = converged ? MC_OK : MC_NOT_CONVERGED;
-    stats->iters = it;
-    stats->cert_gap = cert;
-    stats->energy = energy;
-    stats->lower_bound = lb;
-    stats->tv_gap = tvgap;
-    stats->tau_used = tau_used;
-    stats->ms = ms;
-    MC_HIP(tm.drain());
-    stats->sweep_ms = tm.ms;
-    stats->sweep_launches = tm.launches;
-    stats->checks = checks;
-    return stats->status;
+    return finish_solve(c, g, zc, R * n, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
 }
 
 }  // namespace
@@ -337,6 +472,7 @@ int mc_ctx_destroy(mc_ctx* c)
     (void)hipFree(c->bmeta);
     (void)hipFree(c->nbuf);
     (void)hipFree(c->g8buf);
+    (void)hipFree(c->vbuf);
     if (c->bstream) (void)hipStreamDestroy(c->bstream);
     delete c;
     return MC_OK;
@@ -401,6 +537,8 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
             if (!a[j]) return fail(MC_ERR_INVALID_ARG, "null weight array");
         return solve8(c, g, w, a, z0, x_out, labels_out, z_out, stats, o, (hipStream_t)stream);
     }
+    if (o.variant == MC_VARIANT_BCD || o.variant == MC_VARIANT_AP || o.variant == MC_VARIANT_FISTA)
+        return solve_variant(c, g, w, a, z0, x_out, labels_out, z_out, stats, o, (hipStream_t)stream);
     bool two_set;
     if (o.variant == MC_VARIANT_AUTO) two_set = g.ndim == 2;
     else if (o.variant == MC_VARIANT_TWO_SET) two_set = true;
@@ -427,13 +565,11 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
 
     const float* pj[3] = {c->p, c->p + n, c->p + 2 * n};
     SweepTimer tm{c, (o.flags & MC_PROFILE) != 0};
-    int checks = 0;
     float taus[kNumTau];
     tau_ladder(o.tau0, taus);
+    CheckState st;
     int it = 0;
     bool converged = false;
-    double cert = INFINITY, energy = INFINITY, lb = -INFINITY, tvgap = NAN;
-    float tau_used = 0.f;
     float* zc = c->z;   // current state
     float* zn = c->z2;  // next state
     while (it < o.max_iters) {
@@ -473,47 +609,14 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
         zc = zn;
         zn = zt;
         if (!check) continue;
-        ++checks;
-        MC_HIP(launch_cert(g, w, a, pj, o.tau0, c->xt, c->partials, c->dout, s));
-        MC_HIP(hipMemcpyAsync(c->hout, c->dout, kCertValues * sizeof(double), hipMemcpyDeviceToHost, s));
-        MC_HIP(hipStreamSynchronize(s));
-        MC_HIP(tm.drain());
-        energy = INFINITY;
-        for (int k = 0; k < kNumTau; ++k) {
-            if (c->hout[k] < energy) {
-                energy = c->hout[k];
-                tau_used = taus[k];
-            }
-        }
-        tvgap = c->hout[kNumTau];
-        lb = c->hout[kNumTau + 1];
-        cert = energy - lb;
-        if (!isfinite(cert)) return fail(MC_ERR_NUMERIC, "non-finite certificate (NaN/Inf in the state)");
-        if (cert < o.gap_tol) {
+        bool done = false;
+        if ((rc = run_check(c, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
+        if (done) {
             converged = true;
             break;
         }
     }
-    MC_HIP(hipEventRecord(c->ev1, s));
-    MC_HIP(launch_labels(g, c->xt, tau_used, labels_out, s));
-    if (x_out) MC_HIP(hipMemcpyAsync(x_out, c->xt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
-    if (z_out) MC_HIP(hipMemcpyAsync(z_out, zc, sizeof(float) * nz, hipMemcpyDeviceToDevice, s));
-    MC_HIP(hipStreamSynchronize(s));
-    float ms = 0.f;
-    MC_HIP(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-    stats->status = converged ? MC_OK : MC_NOT_CONVERGED;
-    stats->iters = it;
-    stats->cert_gap = cert;
-    stats->energy = energy;
-    stats->lower_bound = lb;
-    stats->tv_gap = tvgap;
-    stats->tau_used = tau_used;
-    stats->ms = ms;
-    MC_HIP(tm.drain());
-    stats->sweep_ms = tm.ms;
-    stats->sweep_launches = tm.launches;
-    stats->checks = checks;
-    return stats->status;
+    return finish_solve(c, g, zc, nz, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
 }
 
 }  // extern "C"

@@ -37,6 +37,10 @@ struct mc_ctx {
     size_t g8cap = 0;       // floats in g8buf
     float* g8buf = nullptr;
 
+    // other outer iterations (BCD, AP, FISTA)
+    size_t vcap = 0;        // floats in vbuf
+    float* vbuf = nullptr;
+
     // warm-start network
     size_t ncap = 0;        // bytes in nbuf
     char* nbuf = nullptr;   // packed weights, activations, gradients, partials

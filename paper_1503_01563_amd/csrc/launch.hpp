@@ -104,6 +104,18 @@ hipError_t launch_energy8(const Geo& g, const float* w, const float* const* a, c
 hipError_t launch_validate8(const Geo& g, const float* w, const float* const* a, double* partials, double* out,
                             hipStream_t s);
 
+// ---- elementwise steps of the other outer iterations (BCD, AP, FISTA) ----------
+hipError_t launch_neg(size_t n, const float* w, float* x, hipStream_t s);                     // x = -w
+hipError_t launch_add(size_t n, const float* x, const float* y, float* v, hipStream_t s);     // v = x + y
+hipError_t launch_rsub(size_t n, const float* a, float* d, hipStream_t s);                   // d = a - d
+hipError_t launch_sub(size_t n, const float* a, float* d, hipStream_t s);                    // d = d - a
+hipError_t launch_diff(size_t n, const float* a, const float* b, float* d, hipStream_t s);    // d = a - b
+// AP: y_j = l_j - q_j, x = -w - sum y_j, l_j = y_j + x / r (cold: l_j = -w / r)
+hipError_t launch_ap_update(size_t n, int r, float* lam, const float* q, const float* w, bool cold, hipStream_t s);
+// FISTA: yt = y + beta (y - yp), xt = -w - sum yt_j, v_j = yt_j + xt / r
+hipError_t launch_fista_pre(size_t n, int r, const float* y, const float* yp, float beta, const float* w, float* v,
+                            hipStream_t s);
+
 // Certificate from the edge duals p: primal xc = -w - sum_j D_j^T p_j (FP32
 // out), then out[kCertValues] = {E(S_t) for the ladder, TV gap, LB} in FP64.
 // partials needs kCertValues * kReduceBlocks doubles.

@@ -28,6 +28,7 @@ MC_NOT_CONVERGED = 1
 MC_VALIDATE = 1
 MC_PROFILE = 2
 VARIANT_AUTO, VARIANT_TWO_SET, VARIANT_PRODUCT = 0, 1, 2
+VARIANT_BCD, VARIANT_AP, VARIANT_FISTA = 3, 4, 5
 
 
 class McError(RuntimeError):
@@ -215,7 +216,7 @@ def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tens
     ap = _aptrs(a, shape, nd)
     conn = _conn_of(a, nd)
     two_set = conn != 8 and ((variant == VARIANT_TWO_SET) or (variant == VARIANT_AUTO and nd == 2))
-    nz = w.numel() if two_set else (4 if conn == 8 else nd) * w.numel()
+    nz = w.numel() if two_set else (4 if conn == 8 else nd) * w.numel()  # product space / BCD / AP / FISTA: r*n
     z0p = None
     if z0 is not None:
         if z0.device != w.device or z0.dtype != torch.float32 or not z0.is_contiguous() or z0.numel() != nz:
