@@ -406,11 +406,26 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     }
 }
 
+// Workgroups of a launch are dealt to the chip's eight XCDs in turn
+// (workgroup b runs on XCD b mod 8), and each XCD has its own L2.  Neighbouring
+// pieces of a chain group stage overlapping windows, so they should share an
+// L2: workgroup b takes work item xcd_item(b, n), which gives XCD x the
+// contiguous run of items [x q + min(x, r), ...) (n = 8 q + r; XCDs below r
+// get q + 1 workgroups).  A bijection of [0, n).
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ int xcd_item(int b, int n)
+{
+    const int q = n / kXcds, r = n - q * kXcds;
+    const int x = b % kXcds, j = b / kXcds;
+    return x * q + (x < r ? x : r) + j;
+}
+
 template <class M, bool kRows, bool kExact>
 __global__ void __launch_bounds__(kLanes) k_sweep(Geo g, int axis, M mode, PieceCfg cfg)
 {
     extern __shared__ __attribute__((aligned(16))) float lds[];
-    sweep_piece<M, kRows, kExact>(g, axis, blockIdx.x, mode, cfg, lds);
+    sweep_piece<M, kRows, kExact>(g, axis, xcd_item(blockIdx.x, gridDim.x), mode, cfg, lds);
 }
 
 // the two non-final families of the 3D product space in one launch:
@@ -420,10 +435,11 @@ __global__ void __launch_bounds__(kLanes)
 k_sweep_pair(Geo g, ModeSweepP m0, ModeSweepP m1, PieceCfg c0, PieceCfg c1, int n0)
 {
     extern __shared__ __attribute__((aligned(16))) float lds[];
-    if ((int)blockIdx.x < n0)
-        sweep_piece<ModeSweepP, true, kExact>(g, 0, blockIdx.x, m0, c0, lds);
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item < n0)
+        sweep_piece<ModeSweepP, true, kExact>(g, 0, item, m0, c0, lds);
     else
-        sweep_piece<ModeSweepP, false, kExact>(g, 1, blockIdx.x - n0, m1, c1, lds);
+        sweep_piece<ModeSweepP, false, kExact>(g, 1, item - n0, m1, c1, lds);
 }
 
 inline int items_of(const Geo& g, int axis, const PieceCfg& cfg)
@@ -461,22 +477,24 @@ template <bool kExact>
 __global__ void __launch_bounds__(kLanes) k_batch_rows(BatchLaunch b, int parity)
 {
     extern __shared__ __attribute__((aligned(16))) float lds[];
-    const int gi = b.item_grid_r[blockIdx.x];
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    const int gi = b.item_grid_r[item];
     const BatchGrid& t = b.tab[gi];
     if (t.done) return;
     ModeRows2 m{t.z[parity], t.ax, t.q1, kExact ? t.p : nullptr};
-    sweep_piece<ModeRows2, true, kExact>(t.g, 0, (int)blockIdx.x - t.item0_r, m, t.cr, lds);
+    sweep_piece<ModeRows2, true, kExact>(t.g, 0, item - t.item0_r, m, t.cr, lds);
 }
 
 template <bool kExact>
 __global__ void __launch_bounds__(kLanes) k_batch_cols(BatchLaunch b, int parity)
 {
     extern __shared__ __attribute__((aligned(16))) float lds[];
-    const int gi = b.item_grid_c[blockIdx.x];
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    const int gi = b.item_grid_c[item];
     const BatchGrid& t = b.tab[gi];
     if (t.done) return;
     ModeCols2 m{t.q1, t.z[parity], t.z[parity ^ 1], t.w, t.ay, kExact ? t.p + t.g.n : nullptr};
-    sweep_piece<ModeCols2, false, kExact>(t.g, 1, (int)blockIdx.x - t.item0_c, m, t.cc, lds);
+    sweep_piece<ModeCols2, false, kExact>(t.g, 1, item - t.item0_c, m, t.cc, lds);
 }
 
 // cold start: the row prox of z = 0 is 0 for every grid (blockIdx.y = grid)
