@@ -107,7 +107,7 @@ typedef struct {
     float tau_used;       /* threshold of the returned labels */
     float ms;             /* device time of the solve (hipEvent), milliseconds */
     double sweep_ms;      /* MC_PROFILE: summed device time of the chain-sweep launches */
-    int32_t sweep_launches; /* MC_PROFILE: number of chain-sweep launches timed */
+    int32_t sweep_launches; /* number of chain-sweep launches (counted with or without MC_PROFILE) */
     int32_t checks;       /* certificate evaluations performed */
     int32_t items;        /* batched solves: work items per sweep launch used */
     int32_t reserved2;

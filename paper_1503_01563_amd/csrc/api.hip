@@ -88,8 +88,9 @@ int ensure_ws(mc_ctx* c, size_t n, int r)
     return MC_OK;
 }
 
-// MC_PROFILE: a pool of event pairs bracketing sweep launches, drained at
-// every synchronisation point of the solve.
+// Counts the chain-sweep launches; with MC_PROFILE also brackets each with a
+// pair of events from a pool, drained at every synchronisation point of the
+// solve.  (An event record costs a few microseconds of stream time.)
 struct SweepTimer {
     mc_ctx* c;
     bool on;
@@ -111,10 +112,10 @@ struct SweepTimer {
     }
     hipError_t end(hipStream_t s)
     {
+        ++launches;
         if (!on) return hipSuccess;
         hipError_t r = hipEventRecord(c->prof_ev[used + 1], s);
         used += 2;
-        ++launches;
         return r;
     }
     // call after the stream has been synchronised

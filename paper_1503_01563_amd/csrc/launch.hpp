@@ -44,8 +44,9 @@ constexpr int kLatencyItems = 2048;
 // dynamic LDS bytes of a sweep launch with these pieces
 size_t piece_lds_bytes(const PieceCfg& cfg);
 
-constexpr int kReduceBlocks = 512;   // blocks of the reduction kernels (fixed: deterministic)
+constexpr int kReduceBlocks = 2048;  // blocks of the reduction kernels (fixed: deterministic)
 constexpr int kReduceThreads = 256;
+static_assert(kReduceBlocks % kReduceThreads == 0, "the finalize kernels read whole rounds of partials");
 // Rounding readout: S_t = {x > tau_t} for the decreasing threshold ladder
 // tau0 * (1, 1e-1, 1e-2, 1e-3, 0, -1e-3, -1e-2, -1e-1, -1).
 constexpr int kNumTau = 9;

@@ -51,11 +51,38 @@ k_finalize(const double* __restrict__ partials, int nblk, double* __restrict__ o
     double v[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += kReduceThreads) {
+    // nblk <= kReduceBlocks: a fixed number of rounds, loads of all rounds in flight together
 #pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] += partials[b * NV + q];
+    for (int k = 0; k < kReduceBlocks / kReduceThreads; ++k) {
+        const int b = threadIdx.x + k * kReduceThreads;
+        if (b < nblk) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[q] += partials[b * NV + q];
+        }
     }
     block_reduce_store<NV>(v, out);
+}
+
+// both reductions of the certificate in one block: out[0..kNumTau] from the
+// ladder partials (kNumTau + 1 per block), out[kNumTau + 1] from the
+// lower-bound partials (one per block)
+__global__ void __launch_bounds__(kReduceThreads)
+k_finalize_cert(const double* __restrict__ part_cut, const double* __restrict__ part_lb, int nblk,
+                double* __restrict__ out)
+{
+    double v[kNumTau + 2];
+#pragma unroll
+    for (int q = 0; q < kNumTau + 2; ++q) v[q] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kReduceBlocks / kReduceThreads; ++k) {
+        const int b = threadIdx.x + k * kReduceThreads;
+        if (b < nblk) {
+#pragma unroll
+            for (int q = 0; q <= kNumTau; ++q) v[q] += part_cut[b * (kNumTau + 1) + q];
+            v[kNumTau + 1] += part_lb[b];
+        }
+    }
+    block_reduce_store<kNumTau + 2>(v, out);
 }
 
 struct Coords {
@@ -77,6 +104,41 @@ struct Ptr3 {
     const float* p[3];
 };
 
+// Grid-stride walk over the voxels that carries the coordinates along: one
+// division per thread at the start, then at most one carry per axis per step
+// (x + sx < 2W and y + sy + 1 < 2H since both parts of the stride are reduced).
+struct Walk {
+    int i, stride;
+    Coords c;
+    int sx, sy, sd;
+
+    __device__ __forceinline__ Walk(const Geo& g)
+        : Walk(g, blockIdx.x * kReduceThreads + threadIdx.x, gridDim.x * kReduceThreads)
+    {
+    }
+    __device__ __forceinline__ Walk(const Geo& g, int start, int step)
+    {
+        stride = step;
+        i = start;
+        c = coords_of(g, i < g.n ? i : 0);
+        const Coords s = coords_of(g, stride);
+        sx = s.x;
+        sy = s.y;
+        sd = s.d;
+    }
+    __device__ __forceinline__ void next(const Geo& g)
+    {
+        i += stride;
+        c.x += sx;
+        const int cx = c.x >= g.W ? 1 : 0;
+        c.x -= cx ? g.W : 0;
+        c.y += sy + cx;
+        const int cy = c.y >= g.H ? 1 : 0;
+        c.y -= cy ? g.H : 0;
+        c.d += sd + cy;
+    }
+};
+
 // Primal estimate and lower bound from the edge duals (Sec. 2.2, 2.3):
 // y = sum_j D_j^T p_j with p clipped to its box (so y lies in K exactly),
 // x = -w - y (the TV primal x = w - y in the paper's sign), and
@@ -84,10 +146,9 @@ struct Ptr3 {
 // duals, which stay bounded by the weights, unlike the diverging state.
 // Returns the voxel's LB term and writes its primal.
 __device__ __forceinline__ double primal_voxel(const Geo& g, const float* __restrict__ w,
-                                               const Ptr3& p, float* __restrict__ xc, int i)
+                                               const Ptr3& p, float* __restrict__ xc, int i, const Coords& c)
 {
     const int st[3] = {1, g.W, g.W * g.H};
-    const Coords c = coords_of(g, i);
     const int cc[3] = {c.x, c.y, c.d};
     double y = 0.0;
     for (int j = 0; j < g.ndim; ++j) {
@@ -104,9 +165,7 @@ k_primal(Geo g, const float* __restrict__ w, Ptr3 p, float* __restrict__ xc,
          double* __restrict__ partials)
 {
     double lb = 0.0;
-    const int stride = gridDim.x * kReduceThreads;
-    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride)
-        lb += primal_voxel(g, w, p, xc, i);
+    for (Walk k(g); k.i < g.n; k.next(g)) lb += primal_voxel(g, w, p, xc, k.i, k.c);
     double v[1] = {lb};
     block_reduce_store<1>(v, partials + blockIdx.x);
 }
@@ -128,32 +187,52 @@ __device__ __forceinline__ int ladder_count(float x, const Taus& tz)
     return c;
 }
 
+// Ladder accumulators: e[t] for the thresholds, e[kNumTau] the TV-gap term.
+// Written without branches: the predicated adds cost less than exec-mask
+// regions, which also keep the loads of the next edges from being issued early.
+struct Ladder {
+    double e[kNumTau + 1];
+
+    __device__ __forceinline__ Ladder()
+    {
+#pragma unroll
+        for (int t = 0; t <= kNumTau; ++t) e[t] = 0.0;
+    }
+    // a node with cnt = c is in S_t for t >= c
+    __device__ __forceinline__ void node(int c, double wv)
+    {
+#pragma unroll
+        for (int t = 0; t < kNumTau; ++t)
+            if (t >= c) e[t] += wv;
+    }
+    // an edge between nodes of cnt cu and cv is cut for t in [min, max)
+    __device__ __forceinline__ void edge(int cu, int cv, double av)
+    {
+        const int lo = cu < cv ? cu : cv, hi = cu < cv ? cv : cu;
+#pragma unroll
+        for (int t = 0; t < kNumTau; ++t)
+            if (t >= lo && t < hi) e[t] += av;
+    }
+};
+
 __device__ __forceinline__ void cut_voxel(const Geo& g, const float* __restrict__ xc,
                                           const float* __restrict__ w, const Ptr3& a,
-                                          const Ptr3& p, const Taus& tz, int i,
-                                          double (&e)[kNumTau + 1])
+                                          const Ptr3& p, const Taus& tz, int i, const Coords& c,
+                                          Ladder& L)
 {
     const int st[3] = {1, g.W, g.W * g.H};
-    const Coords c = coords_of(g, i);
     const int cc[3] = {c.x, c.y, c.d};
     const int ext[3] = {g.W, g.H, g.D};
     const float xi = xc[i];
     const int ci = ladder_count(xi, tz);
-    const double wi = (double)w[i];
-#pragma unroll
-    for (int t = 0; t < kNumTau; ++t)
-        if (t >= ci) e[t] += wi;
+    L.node(ci, (double)w[i]);
     for (int j = 0; j < g.ndim; ++j) {
         if (cc[j] + 1 < ext[j]) {
             const float xn = xc[i + st[j]];
-            const int cn = ladder_count(xn, tz);
             const double aj = (double)a.p[j][i];
-            const int lo = ci < cn ? ci : cn, hi = ci < cn ? cn : ci;
-#pragma unroll
-            for (int t = 0; t < kNumTau; ++t)
-                if (t >= lo && t < hi) e[t] += aj;
+            L.edge(ci, ladder_count(xn, tz), aj);
             const double dx = (double)xn - (double)xi;
-            e[kNumTau] += aj * fabs(dx) - (double)p.p[j][i] * dx;
+            L.e[kNumTau] += aj * fabs(dx) - (double)p.p[j][i] * dx;
         }
     }
 }
@@ -162,13 +241,9 @@ __global__ void __launch_bounds__(kReduceThreads)
 k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, Ptr3 a, Ptr3 p,
              Taus tz, double* __restrict__ partials)
 {
-    double e[kNumTau + 1];
-#pragma unroll
-    for (int t = 0; t <= kNumTau; ++t) e[t] = 0.0;
-    const int stride = gridDim.x * kReduceThreads;
-    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride)
-        cut_voxel(g, xc, w, a, p, tz, i, e);
-    block_reduce_store<kNumTau + 1>(e, partials + (size_t)blockIdx.x * (kNumTau + 1));
+    Ladder L;
+    for (Walk k(g); k.i < g.n; k.next(g)) cut_voxel(g, xc, w, a, p, tz, k.i, k.c, L);
+    block_reduce_store<kNumTau + 1>(L.e, partials + (size_t)blockIdx.x * (kNumTau + 1));
 }
 
 // ---- 8-connected 2D grids -------------------------------------------------------
@@ -184,9 +259,9 @@ struct Ptr4 {
 };
 
 __device__ __forceinline__ double primal8_voxel(const Geo& g, const float* __restrict__ w, const Ptr4& p,
-                                                float* __restrict__ xc, int i)
+                                                float* __restrict__ xc, int i, int r, int c)
 {
-    const int W = g.W, r = i / W, c = i - r * W;
+    const int W = g.W;
     // left end of its own row, column and diagonal edges
     double y = -(double)p.p[0][i] - (double)p.p[1][i] - (double)p.p[2][i];
     if (c > 0) y += (double)p.p[0][i - 1];
@@ -203,55 +278,42 @@ __global__ void __launch_bounds__(kReduceThreads)
 k_primal8(Geo g, const float* __restrict__ w, Ptr4 p, float* __restrict__ xc, double* __restrict__ partials)
 {
     double lb = 0.0;
-    const int stride = gridDim.x * kReduceThreads;
-    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride)
-        lb += primal8_voxel(g, w, p, xc, i);
+    for (Walk k(g); k.i < g.n; k.next(g)) lb += primal8_voxel(g, w, p, xc, k.i, k.c.y, k.c.x);
     double v[1] = {lb};
     block_reduce_store<1>(v, partials + blockIdx.x);
 }
 
 // one edge u-v of weight ae and dual pe: ladder energies and TV-gap term
-__device__ __forceinline__ void cut_edge(float xu, int cu, float xv, double ae, double pe, const Taus& tz,
-                                         const float* __restrict__ xc, int v, double (&e)[kNumTau + 1])
+__device__ __forceinline__ void cut_edge(float xu, int cu, double ae, double pe, const Taus& tz,
+                                         const float* __restrict__ xc, int v, Ladder& L)
 {
-    (void)xv;
     const float xn = xc[v];
-    const int cn = ladder_count(xn, tz);
-    const int lo = cu < cn ? cu : cn, hi = cu < cn ? cn : cu;
-#pragma unroll
-    for (int t = 0; t < kNumTau; ++t)
-        if (t >= lo && t < hi) e[t] += ae;
+    L.edge(cu, ladder_count(xn, tz), ae);
     const double dx = (double)xn - (double)xu;
-    e[kNumTau] += ae * fabs(dx) - pe * dx;
+    L.e[kNumTau] += ae * fabs(dx) - pe * dx;
 }
 
 __global__ void __launch_bounds__(kReduceThreads)
 k_cut_ladder8(Geo g, const float* __restrict__ xc, const float* __restrict__ w, Ptr4 a, Ptr4 p, Taus tz,
               double* __restrict__ partials)
 {
-    double e[kNumTau + 1];
-#pragma unroll
-    for (int t = 0; t <= kNumTau; ++t) e[t] = 0.0;
-    const int stride = gridDim.x * kReduceThreads;
+    Ladder L;
     const int W = g.W, H = g.H;
-    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
-        const int r = i / W, c = i - r * W;
+    for (Walk k(g); k.i < g.n; k.next(g)) {
+        const int i = k.i, r = k.c.y, c = k.c.x;
         const float xi = xc[i];
         const int ci = ladder_count(xi, tz);
-        const double wi = (double)w[i];
-#pragma unroll
-        for (int t = 0; t < kNumTau; ++t)
-            if (t >= ci) e[t] += wi;
-        if (c + 1 < W) cut_edge(xi, ci, 0.f, (double)a.p[0][i], (double)p.p[0][i], tz, xc, i + 1, e);
-        if (r + 1 < H) cut_edge(xi, ci, 0.f, (double)a.p[1][i], (double)p.p[1][i], tz, xc, i + W, e);
+        L.node(ci, (double)w[i]);
+        if (c + 1 < W) cut_edge(xi, ci, (double)a.p[0][i], (double)p.p[0][i], tz, xc, i + 1, L);
+        if (r + 1 < H) cut_edge(xi, ci, (double)a.p[1][i], (double)p.p[1][i], tz, xc, i + W, L);
         if (r + 1 < H && c + 1 < W) {
-            cut_edge(xi, ci, 0.f, (double)a.p[2][i], (double)p.p[2][i], tz, xc, i + W + 1, e);
+            cut_edge(xi, ci, (double)a.p[2][i], (double)p.p[2][i], tz, xc, i + W + 1, L);
             // anti-diagonal of cell (r, c): from (r+1, c) to (r, c+1)
             const float xu = xc[i + W];
-            cut_edge(xu, ladder_count(xu, tz), 0.f, (double)a.p[3][i], (double)p.p[3][i], tz, xc, i + 1, e);
+            cut_edge(xu, ladder_count(xu, tz), (double)a.p[3][i], (double)p.p[3][i], tz, xc, i + 1, L);
         }
     }
-    block_reduce_store<kNumTau + 1>(e, partials + (size_t)blockIdx.x * (kNumTau + 1));
+    block_reduce_store<kNumTau + 1>(L.e, partials + (size_t)blockIdx.x * (kNumTau + 1));
 }
 
 __global__ void __launch_bounds__(kReduceThreads)
@@ -314,9 +376,9 @@ k_batch_primal(BatchLaunch b, double* __restrict__ partials)
     if (t.done) return;
     const Ptr3 p = batch_duals(t);
     double lb = 0.0;
-    const int stride = t.nblk * kReduceThreads;
-    for (int i = ((int)blockIdx.x - t.blk0) * kReduceThreads + threadIdx.x; i < t.g.n; i += stride)
-        lb += primal_voxel(t.g, t.w, p, t.xc, i);
+    for (Walk k(t.g, ((int)blockIdx.x - t.blk0) * kReduceThreads + threadIdx.x, t.nblk * kReduceThreads); k.i < t.g.n;
+         k.next(t.g))
+        lb += primal_voxel(t.g, t.w, p, t.xc, k.i, k.c);
     double v[1] = {lb};
     block_reduce_store<1>(v, partials + (size_t)blockIdx.x * kCertValues + kNumTau + 1);
 }
@@ -331,13 +393,11 @@ k_batch_cut(BatchLaunch b, Taus tz, double* __restrict__ partials)
     a.p[1] = t.ay;
     a.p[2] = nullptr;
     const Ptr3 p = batch_duals(t);
-    double e[kNumTau + 1];
-#pragma unroll
-    for (int k = 0; k <= kNumTau; ++k) e[k] = 0.0;
-    const int stride = t.nblk * kReduceThreads;
-    for (int i = ((int)blockIdx.x - t.blk0) * kReduceThreads + threadIdx.x; i < t.g.n; i += stride)
-        cut_voxel(t.g, t.xc, t.w, a, p, tz, i, e);
-    block_reduce_store<kNumTau + 1>(e, partials + (size_t)blockIdx.x * kCertValues);
+    Ladder L;
+    for (Walk k(t.g, ((int)blockIdx.x - t.blk0) * kReduceThreads + threadIdx.x, t.nblk * kReduceThreads); k.i < t.g.n;
+         k.next(t.g))
+        cut_voxel(t.g, t.xc, t.w, a, p, tz, k.i, k.c, L);
+    block_reduce_store<kNumTau + 1>(L.e, partials + (size_t)blockIdx.x * kCertValues);
 }
 
 // one block per grid: fixed-order sum of the grid's block partials, then the
@@ -413,11 +473,10 @@ k_energy(Geo g, const float* __restrict__ w, Ptr3 a, const uint8_t* __restrict__
          double* __restrict__ partials)
 {
     double e = 0.0;
-    const int stride = gridDim.x * kReduceThreads;
     const int st[3] = {1, g.W, g.W * g.H};
-    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
-        const Coords c = coords_of(g, i);
-        const int cc[3] = {c.x, c.y, c.d};
+    for (Walk k(g); k.i < g.n; k.next(g)) {
+        const int i = k.i;
+        const int cc[3] = {k.c.x, k.c.y, k.c.d};
         const int ext[3] = {g.W, g.H, g.D};
         const bool b = lab[i] != 0;
         if (b) e += (double)w[i];
@@ -435,10 +494,9 @@ __global__ void __launch_bounds__(kReduceThreads)
 k_validate(Geo g, const float* __restrict__ w, Ptr3 a, double* __restrict__ partials)
 {
     double bad_w = 0.0, nonfin = 0.0;
-    const int stride = gridDim.x * kReduceThreads;
-    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < g.n; i += stride) {
-        const Coords c = coords_of(g, i);
-        const int cc[3] = {c.x, c.y, c.d};
+    for (Walk k(g); k.i < g.n; k.next(g)) {
+        const int i = k.i;
+        const int cc[3] = {k.c.x, k.c.y, k.c.d};
         const int ext[3] = {g.W, g.H, g.D};
         if (!isfinite(w[i])) nonfin += 1.0;
         for (int j = 0; j < g.ndim; ++j) {
@@ -497,10 +555,7 @@ hipError_t launch_cert(const Geo& g, const float* w, const float* const* a,
     hipLaunchKernelGGL(k_primal, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pp, xc, part_lb);
     hipLaunchKernelGGL(k_cut_ladder, dim3(nb), dim3(kReduceThreads), 0, s, g, xc, w, pa, pp, tz,
                        part_cut);
-    hipLaunchKernelGGL(k_finalize<kNumTau + 1>, dim3(1), dim3(kReduceThreads), 0, s, part_cut, nb,
-                       out);
-    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, part_lb, nb,
-                       out + kNumTau + 1);
+    hipLaunchKernelGGL(k_finalize_cert, dim3(1), dim3(kReduceThreads), 0, s, part_cut, part_lb, nb, out);
     return hipGetLastError();
 }
 
@@ -519,8 +574,7 @@ hipError_t launch_cert8(const Geo& g, const float* w, const float* const* a, con
     double* part_lb = partials + (size_t)nb * (kNumTau + 1);
     hipLaunchKernelGGL(k_primal8, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pp, xc, part_lb);
     hipLaunchKernelGGL(k_cut_ladder8, dim3(nb), dim3(kReduceThreads), 0, s, g, xc, w, pa, pp, tz, part_cut);
-    hipLaunchKernelGGL(k_finalize<kNumTau + 1>, dim3(1), dim3(kReduceThreads), 0, s, part_cut, nb, out);
-    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, part_lb, nb, out + kNumTau + 1);
+    hipLaunchKernelGGL(k_finalize_cert, dim3(1), dim3(kReduceThreads), 0, s, part_cut, part_lb, nb, out);
     return hipGetLastError();
 }
 
