@@ -409,16 +409,21 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
 // Workgroups of a launch are dealt to the chip's eight XCDs in turn
 // (workgroup b runs on XCD b mod 8), and each XCD has its own L2.  Neighbouring
 // pieces of a chain group stage overlapping windows, so they should share an
-// L2: workgroup b takes work item xcd_item(b, n), which gives XCD x the
-// contiguous run of items [x q + min(x, r), ...) (n = 8 q + r; XCDs below r
-// get q + 1 workgroups).  A bijection of [0, n).
+// L2; the work of a launch (grids of a batch that finish at different times)
+// should still spread over all XCDs.  xcd_item gives each XCD runs of kXcdRun
+// consecutive work items, the runs dealt to the XCDs in turn: workgroup b,
+// the j-th on its XCD x = b mod 8, takes item ((j / kXcdRun) * 8 + x) * kXcdRun
+// + j mod kXcdRun.  Items past the last whole round of runs keep their index.
+// A bijection of [0, n).
 constexpr int kXcds = 8;
+constexpr int kXcdRun = 16;
 
 __device__ __forceinline__ int xcd_item(int b, int n)
 {
-    const int q = n / kXcds, r = n - q * kXcds;
+    const int round = kXcds * kXcdRun;
+    if (b >= n / round * round) return b;
     const int x = b % kXcds, j = b / kXcds;
-    return x * q + (x < r ? x : r) + j;
+    return ((j / kXcdRun) * kXcds + x) * kXcdRun + j % kXcdRun;
 }
 
 template <class M, bool kRows, bool kExact>
