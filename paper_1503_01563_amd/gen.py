@@ -23,6 +23,12 @@ stand in for them):
                          an integer grid whose unaries are partly redrawn per
                          frame (related problems for reusing one frame's dual
                          in the next).
+  * ``stereo_labels``  -- a multi-label problem shaped like a small stereo
+                         task (piecewise-constant label map: a tilted
+                         background plane and objects at constant labels,
+                         noisy observed labels with outliers): integer data
+                         costs D[l] = min(|obs - l|, t_data), integer edge
+                         weights that drop across intensity edges.
 """
 from __future__ import annotations
 
@@ -161,6 +167,40 @@ def ellipse_sequence(shape, seed, frames, speed=2.0, lam=2.0, sigma=0.15, beta_s
         moved = [(c + t * v, semi, rot) for (c, semi, rot), v in zip(ells, vel)]
         out.append(_image_to_grid(_render(shape, moved, rng, sigma), lam, sigma, beta_sigma))
     return out
+
+
+def stereo_labels(shape, seed, n_labels=16, sigma=1.2, outliers=0.1, t_data=8, lam_hi=3, lam_lo=1,
+                  k_range=(6, 12)):
+    """Multi-label problem on an (H, W) grid: (data [L][H][W], [lam_x, lam_y],
+    true labels).  Integer values, so every energy is exact; lam_x's last
+    column and lam_y's last row are zero."""
+    rng = _rng(seed)
+    H, W = (int(s) for s in shape)
+    L = int(n_labels)
+    # background: a plane tilted along W, objects at constant labels on top
+    lo, hi = sorted(rng.integers(0, L // 2, size=2))
+    true = np.broadcast_to(np.floor(np.linspace(lo, hi + 0.999, W)), (H, W)).astype(np.int64).copy()
+    grids = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
+    coords = np.stack([g.ravel() for g in grids], axis=1)
+    for centre, semi, rot in _ellipses(rng, (H, W), k_range):
+        d = (coords - centre) @ rot
+        inside = (np.sum((d / semi) ** 2, axis=1) <= 1.0).reshape(H, W)
+        true[inside] = int(rng.integers(0, L))
+    # observed labels: noise, then outliers anywhere in the label range
+    obs = np.rint(true + rng.normal(0.0, sigma, size=(H, W)))
+    out = rng.uniform(size=(H, W)) < outliers
+    obs[out] = rng.integers(0, L, size=int(out.sum()))
+    labels = np.arange(L, dtype=np.float64)[:, None, None]
+    data = np.minimum(np.abs(obs[None] - labels), t_data).astype(np.float32)
+    # an intensity image with edges where the labels change sets the weights
+    img = 8.0 * true + rng.normal(0.0, 2.0, size=(H, W))
+    lam_x = np.where(np.abs(np.diff(img, axis=1)) <= 6.0, lam_hi, lam_lo).astype(np.float32)
+    lam_y = np.where(np.abs(np.diff(img, axis=0)) <= 6.0, lam_hi, lam_lo).astype(np.float32)
+    lx = np.zeros((H, W), np.float32)
+    ly = np.zeros((H, W), np.float32)
+    lx[:, :-1] = lam_x
+    ly[:-1, :] = lam_y
+    return data, [lx, ly], true.astype(np.int32)
 
 
 def batch_sizes(count, seed, lo=128, hi=1024):
