@@ -65,6 +65,8 @@ extern "C" {
 /* mc_opts.flags */
 #define MC_VALIDATE 1u           /* check inputs on the device before solving */
 #define MC_PROFILE 2u            /* time every chain-sweep launch with hipEvents (mc_stats.sweep_ms) */
+#define MC_WARM_MOVES 4u         /* mc_alpha_expansion: start each move from the primal and row duals
+                                    of the same label's move in the previous cycle (Sec. 4.4) */
 
 /* mc_opts.variant */
 #define MC_VARIANT_AUTO 0        /* two-set form for 2D, product space for 3D */
@@ -93,7 +95,7 @@ typedef struct {
     float tau0;           /* labels S_tau = {x > tau} for the ladder tau = tau0 * (1, 1e-1, 1e-2,
                              1e-3, 0, -1e-3, -1e-2, -1e-1, -1); the first of least energy
                              is returned (default 1e-3) */
-    uint32_t flags;       /* MC_VALIDATE | MC_PROFILE */
+    uint32_t flags;       /* MC_VALIDATE | MC_PROFILE | MC_WARM_MOVES */
     int32_t reserved[4];  /* reserved[0]: work items per sweep launch of batched solves (0 = tuned) */
 } mc_opts;
 
@@ -231,6 +233,78 @@ int mc_ws_adam_step(mc_ctx *ctx, float *params, const float *grad, float *m, flo
  * in the row family's set K exactly.  z0 [H*W] is passed to mc_tv_solve. */
 int mc_ws_warm_state(mc_ctx *ctx, const mc_grid *grid, const float *out,
                      const float *a_x, float c, float *z0, void *stream);
+
+/*
+ * ---- Multi-label energies by alpha-expansion (Sec. 4.4: move-making reduces
+ * a multi-label problem to a series of binary cuts; Sec. 6.1 solves a
+ * 4-connected stereo task that way with the two-set dual). ----
+ *
+ * On a 2D 4-connected grid (grid->ndim = 2, conn 0 or 4), labels f_i in
+ * {0..n_labels-1}:
+ *     E(f) = sum_i data[f_i][i] + sum_{edges e = (u, v)} lam_e V(f_u, f_v)
+ *   data    [n_labels][H][W] label costs (device, FP32).
+ *   lam     host array of 2 device pointers: lam[0][i] weighs (i, i+1) along W
+ *           (last column 0), lam[1][i] weighs (i, i+W) (last row 0); >= 0.
+ *   v_kind  MC_V_POTTS (V = [a != b]) or MC_V_TRUNC_LINEAR
+ *           (V = min(|a - b|, v_trunc), v_trunc >= 0): both metrics, so every
+ *           expansion move is a cut problem with non-negative weights.
+ *   labels  [H][W] int32 device labels; every entry must lie in
+ *           [0, n_labels) (checked on the device: MC_ERR_INVALID_ARG).
+ * The move of label alpha lets each pixel keep f_i or take alpha.  With
+ * A = V(f_u, f_v), B = V(f_u, alpha), C = V(alpha, f_v) its binary problem in
+ * the form of mc_tv_solve (S = pixels that switch) is
+ *     w_i = data[alpha][i] - data[f_i][i] + lam (C - A - B)/2 for each edge with
+ *           i = u, + lam (B - A - C)/2 for each edge with i = v,
+ *     a_e = lam (B + C - A) / 2,
+ * and E(f with S switched) = E(f) + E_bin(S).
+ */
+#define MC_V_POTTS 0
+#define MC_V_TRUNC_LINEAR 1
+
+typedef struct {
+    int32_t status;       /* MC_OK: the last cycle made no improving move (a local
+                             minimum for every expansion); MC_NOT_CONVERGED:
+                             max_cycles reached or some move was not certified */
+    int32_t cycles;       /* cycles over alpha = 0..n_labels-1 */
+    int32_t moves;        /* binary problems solved */
+    int32_t accepted;     /* moves applied (those that lowered E) */
+    int32_t uncertified;  /* moves whose solve stopped at opts->max_iters */
+    int32_t reserved;
+    int64_t dr_iters;     /* splitting iterations over all moves */
+    double energy0;       /* E(f) of the labels passed in, FP64 */
+    double energy;        /* E(f) of the labels returned, FP64 */
+    float ms;             /* wall time of the whole call, milliseconds */
+    float reserved2;
+} mc_ml_stats;
+
+/* The binary problem of one expansion move of label `alpha` from `labels`:
+ * w_out [H][W] and a_out[0], a_out[1] (host array of 2 device pointers,
+ * [H][W] each, last column / row 0), ready for mc_tv_solve.  Asynchronous on
+ * `stream` except for the label check, which synchronises it. */
+int mc_expansion_problem(mc_ctx *ctx, const mc_grid *grid, int n_labels, const float *data,
+                         const float *const *lam, int v_kind, float v_trunc,
+                         const int32_t *labels, int alpha, float *w_out, float *const *a_out,
+                         void *stream);
+
+/* E(f) in FP64 with a fixed reduction order; synchronises `stream`. */
+int mc_ml_energy(mc_ctx *ctx, const mc_grid *grid, int n_labels, const float *data,
+                 const float *const *lam, int v_kind, float v_trunc, const int32_t *labels,
+                 double *energy_out, void *stream);
+
+/* Alpha-expansion from the labels passed in, in place: cycles over
+ * alpha = 0..n_labels-1, each move solved exactly by mc_tv_solve with `opts`
+ * (nullable: defaults; the move's labels are its certified minimum cut) and
+ * applied when its energy is negative, until a cycle applies no move or
+ * max_cycles cycles have run.  With MC_WARM_MOVES the move of a label starts
+ * from z0 = x + D_rows^T clip(p1, -a_x, a_x), x and p1 the primal and row
+ * duals its previous move ended with (the moves in between change the
+ * problem, so this is a starting point, not a solution).  Workspace comes from
+ * the context (3 + 2 n_labels floats per pixel with MC_WARM_MOVES, 3 without);
+ * synchronises `stream`.  With MC_VALIDATE in opts->flags the weights are checked first
+ * (non-finite or negative entries, non-zero last column / row). */
+int mc_alpha_expansion(mc_ctx *ctx, const mc_grid *grid, int n_labels, const float *data,
+                       const float *const *lam, int v_kind, float v_trunc, int32_t *labels,
+                       int max_cycles, mc_ml_stats *stats, const mc_opts *opts, void *stream);
 
 /* Text for a status code, and the calling thread's last error message. */
 const char *mc_status_string(int code);

@@ -25,6 +25,40 @@ int set_error(int code, const std::string& msg)
     return code;
 }
 
+int make_geo(const mc_grid* grid, Geo* g)
+{
+    if (!grid) return set_error(MC_ERR_INVALID_ARG, "grid is null");
+    int64_t D, H, W;
+    if (grid->ndim == 2) {
+        D = 1; H = grid->dims[0]; W = grid->dims[1];
+    } else if (grid->ndim == 3) {
+        D = grid->dims[0]; H = grid->dims[1]; W = grid->dims[2];
+    } else {
+        return set_error(MC_ERR_INVALID_ARG, "ndim must be 2 or 3");
+    }
+    if (D <= 0 || H <= 0 || W <= 0) return set_error(MC_ERR_INVALID_ARG, "dims must be positive");
+    const int64_t n = D * H * W;
+    if (n > INT32_MAX || D > INT32_MAX || H > INT32_MAX || W > INT32_MAX)
+        return set_error(MC_ERR_INVALID_ARG, "grid has more than 2^31-1 nodes");
+    if (W >= (1 << 30) || H >= (1 << 30) || D >= (1 << 30))
+        return set_error(MC_ERR_INVALID_ARG, "chain length must be below 2^30");
+    g->D = (int)D; g->H = (int)H; g->W = (int)W;
+    g->n = (int)n;
+    g->ndim = grid->ndim;
+    if (grid->conn != 0 && grid->conn != 4 && grid->conn != 6 && grid->conn != 8)
+        return set_error(MC_ERR_INVALID_ARG, "conn must be 0, 4, 6 or 8");
+    if (grid->conn == 8 && grid->ndim != 2) return set_error(MC_ERR_INVALID_ARG, "8-connected grids are 2D");
+    return MC_OK;
+}
+
+int check_ctx(mc_ctx* c)
+{
+    if (!c) return set_error(MC_ERR_INVALID_ARG, "ctx is null");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_error(e, "hipSetDevice");
+    return MC_OK;
+}
+
 }  // namespace mc
 
 namespace {
@@ -32,32 +66,6 @@ namespace {
 int fail(int code, const std::string& msg) { return set_error(code, msg); }
 
 int hip_fail(hipError_t e, const char* where) { return hip_error(e, where); }
-
-int make_geo(const mc_grid* grid, Geo* g)
-{
-    if (!grid) return fail(MC_ERR_INVALID_ARG, "grid is null");
-    int64_t D, H, W;
-    if (grid->ndim == 2) {
-        D = 1; H = grid->dims[0]; W = grid->dims[1];
-    } else if (grid->ndim == 3) {
-        D = grid->dims[0]; H = grid->dims[1]; W = grid->dims[2];
-    } else {
-        return fail(MC_ERR_INVALID_ARG, "ndim must be 2 or 3");
-    }
-    if (D <= 0 || H <= 0 || W <= 0) return fail(MC_ERR_INVALID_ARG, "dims must be positive");
-    const int64_t n = D * H * W;
-    if (n > INT32_MAX || D > INT32_MAX || H > INT32_MAX || W > INT32_MAX)
-        return fail(MC_ERR_INVALID_ARG, "grid has more than 2^31-1 nodes");
-    if (W >= (1 << 30) || H >= (1 << 30) || D >= (1 << 30))
-        return fail(MC_ERR_INVALID_ARG, "chain length must be below 2^30");
-    g->D = (int)D; g->H = (int)H; g->W = (int)W;
-    g->n = (int)n;
-    g->ndim = grid->ndim;
-    if (grid->conn != 0 && grid->conn != 4 && grid->conn != 6 && grid->conn != 8)
-        return fail(MC_ERR_INVALID_ARG, "conn must be 0, 4, 6 or 8");
-    if (grid->conn == 8 && grid->ndim != 2) return fail(MC_ERR_INVALID_ARG, "8-connected grids are 2D");
-    return MC_OK;
-}
 
 void free_ws(mc_ctx* c)
 {
@@ -132,13 +140,6 @@ struct SweepTimer {
     }
 };
 
-int check_ctx(mc_ctx* c)
-{
-    if (!c) return fail(MC_ERR_INVALID_ARG, "ctx is null");
-    hipError_t e = hipSetDevice(c->device);
-    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    return MC_OK;
-}
 
 // ---- shared by the solve loops ----------------------------------------------------
 
@@ -474,6 +475,8 @@ int mc_ctx_destroy(mc_ctx* c)
     (void)hipFree(c->nbuf);
     (void)hipFree(c->g8buf);
     (void)hipFree(c->vbuf);
+    (void)hipFree(c->mlbuf);
+    (void)hipFree(c->mlsel);
     if (c->bstream) (void)hipStreamDestroy(c->bstream);
     delete c;
     return MC_OK;

@@ -41,6 +41,12 @@ struct mc_ctx {
     size_t vcap = 0;        // floats in vbuf
     float* vbuf = nullptr;
 
+    // alpha-expansion: move problem (w, a_x, a_y), move labels
+    size_t mlcap = 0;       // pixels the buffers hold
+    size_t mlper = 0;       // floats per pixel in mlbuf
+    float* mlbuf = nullptr; // mlper * mlcap floats
+    uint8_t* mlsel = nullptr;  // mlcap bytes
+
     // warm-start network
     size_t ncap = 0;        // bytes in nbuf
     char* nbuf = nullptr;   // packed weights, activations, gradients, partials
@@ -49,6 +55,12 @@ struct mc_ctx {
 namespace mc {
 
 int set_error(int code, const std::string& msg);
+
+// grid -> Geo with the checks every entry point shares (dims, size limits, conn)
+int make_geo(const mc_grid* grid, Geo* g);
+
+// non-null context, its device made current
+int check_ctx(mc_ctx* c);
 
 inline int hip_error(hipError_t e, const char* where)
 {

@@ -185,4 +185,16 @@ hipError_t launch_validate(const Geo& g, const float* w, const float* const* a,
 hipError_t launch_count_nonfinite(const float* x, int n, double* partials, double* out,
                                   hipStream_t s);
 
+// ---- alpha-expansion (multilabel.hip; checks and energy in reduce.hip) ----
+// out[0] = number of labels outside [0, L)
+hipError_t launch_check_labels(int n, int L, const int32_t* f, double* partials, double* out, hipStream_t s);
+// out[0] = E(f) of the multi-label energy (2D grid, lam[0] along W, lam[1] along H)
+hipError_t launch_ml_energy(const Geo& g, const float* data, const float* const* lam, int kind, float trunc,
+                            const int32_t* f, double* partials, double* out, hipStream_t s);
+// binary problem of the expansion move of `alpha` from f: w, a_x, a_y
+hipError_t launch_expand_build(const Geo& g, const float* data, const float* const* lam, int kind, float trunc,
+                               const int32_t* f, int alpha, float* w, float* ax, float* ay, hipStream_t s);
+// f_i = alpha where sel_i != 0
+hipError_t launch_expand_apply(int n, int alpha, const uint8_t* sel, int32_t* f, hipStream_t s);
+
 }  // namespace mc

@@ -10,6 +10,7 @@
 
 #include "chain.hpp"
 #include "launch.hpp"
+#include "mc.h"
 
 namespace mc {
 
@@ -520,6 +521,45 @@ k_count_nonfinite(const float* __restrict__ x, int n, double* __restrict__ parti
     block_reduce_store<1>(v, partials + blockIdx.x);
 }
 
+// ---- multi-label energies (alpha-expansion) -------------------------------------
+
+// number of labels outside [0, L)
+__global__ void __launch_bounds__(kReduceThreads)
+k_check_labels(int n, int L, const int32_t* __restrict__ f, double* __restrict__ partials)
+{
+    double bad = 0.0;
+    const int stride = gridDim.x * kReduceThreads;
+    for (int i = blockIdx.x * kReduceThreads + threadIdx.x; i < n; i += stride)
+        if (f[i] < 0 || f[i] >= L) bad += 1.0;
+    double v[1] = {bad};
+    block_reduce_store<1>(v, partials + blockIdx.x);
+}
+
+// the pairwise metric: Potts [a != b] or truncated linear min(|a - b|, T)
+__device__ __forceinline__ float ml_v(int kind, float trunc, int a, int b)
+{
+    if (kind == MC_V_POTTS) return a != b ? 1.f : 0.f;
+    const float d = (float)(a > b ? a - b : b - a);
+    return d < trunc ? d : trunc;
+}
+
+// E(f) = sum_i data[f_i][i] + sum_e lam_e V(f_u, f_v): FP64 sums of FP32 terms
+// (each lam_e V a product of two exact FP32 values, formed in FP64)
+__global__ void __launch_bounds__(kReduceThreads)
+k_ml_energy(Geo g, const float* __restrict__ data, const float* __restrict__ lx, const float* __restrict__ ly,
+            int kind, float trunc, const int32_t* __restrict__ f, double* __restrict__ partials)
+{
+    double e = 0.0;
+    for (Walk k(g); k.i < g.n; k.next(g)) {
+        const int i = k.i, fi = f[i];
+        e += (double)data[(size_t)fi * g.n + i];
+        if (k.c.x + 1 < g.W) e += (double)lx[i] * (double)ml_v(kind, trunc, fi, f[i + 1]);
+        if (k.c.y + 1 < g.H) e += (double)ly[i] * (double)ml_v(kind, trunc, fi, f[i + g.W]);
+    }
+    double v[1] = {e};
+    block_reduce_store<1>(v, partials + blockIdx.x);
+}
+
 __global__ void __launch_bounds__(kReduceThreads)
 k_labels(int n, const float* __restrict__ xc, float tau, uint8_t* __restrict__ lab)
 {
@@ -665,6 +705,24 @@ hipError_t launch_validate(const Geo& g, const float* w, const float* const* a,
     const int nb = reduce_blocks(g.n);
     hipLaunchKernelGGL(k_validate, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pa, partials);
     hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kReduceThreads), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_labels(int n, int L, const int32_t* f, double* partials, double* out, hipStream_t s)
+{
+    const int nb = reduce_blocks(n);
+    hipLaunchKernelGGL(k_check_labels, dim3(nb), dim3(kReduceThreads), 0, s, n, L, f, partials);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ml_energy(const Geo& g, const float* data, const float* const* lam, int kind, float trunc,
+                            const int32_t* f, double* partials, double* out, hipStream_t s)
+{
+    const int nb = reduce_blocks(g.n);
+    hipLaunchKernelGGL(k_ml_energy, dim3(nb), dim3(kReduceThreads), 0, s, g, data, lam[0], lam[1], kind, trunc, f,
+                       partials);
+    hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, partials, nb, out);
     return hipGetLastError();
 }
 

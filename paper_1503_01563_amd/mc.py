@@ -27,8 +27,10 @@ MC_OK = 0
 MC_NOT_CONVERGED = 1
 MC_VALIDATE = 1
 MC_PROFILE = 2
+MC_WARM_MOVES = 4
 VARIANT_AUTO, VARIANT_TWO_SET, VARIANT_PRODUCT = 0, 1, 2
 VARIANT_BCD, VARIANT_AP, VARIANT_FISTA = 3, 4, 5
+V_POTTS, V_TRUNC_LINEAR = 0, 1
 
 
 class McError(RuntimeError):
@@ -56,6 +58,13 @@ class Stats(ctypes.Structure):
                 ("tau_used", ctypes.c_float), ("ms", ctypes.c_float),
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
                 ("checks", ctypes.c_int32), ("items", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+
+
+class MLStats(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("cycles", ctypes.c_int32), ("moves", ctypes.c_int32),
+                ("accepted", ctypes.c_int32), ("uncertified", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("dr_iters", ctypes.c_int64), ("energy0", ctypes.c_double), ("energy", ctypes.c_double),
+                ("ms", ctypes.c_float), ("reserved2", ctypes.c_float)]
 
 
 _lib = None
@@ -99,6 +108,13 @@ def load_library():
         lib.mc_ws_adam_step.restype = ctypes.c_int
         lib.mc_ws_warm_state.argtypes = [P, ctypes.POINTER(Grid), P, P, F, P, P]
         lib.mc_ws_warm_state.restype = ctypes.c_int
+        lib.mc_expansion_problem.argtypes = [P, ctypes.POINTER(Grid), I, P, P, I, F, P, I, P, P, P]
+        lib.mc_expansion_problem.restype = ctypes.c_int
+        lib.mc_ml_energy.argtypes = [P, ctypes.POINTER(Grid), I, P, P, I, F, P, ctypes.POINTER(ctypes.c_double), P]
+        lib.mc_ml_energy.restype = ctypes.c_int
+        lib.mc_alpha_expansion.argtypes = [P, ctypes.POINTER(Grid), I, P, P, I, F, P, I,
+                                           ctypes.POINTER(MLStats), ctypes.POINTER(Opts), P]
+        lib.mc_alpha_expansion.restype = ctypes.c_int
         lib.mc_status_string.argtypes = [ctypes.c_int]
         lib.mc_status_string.restype = ctypes.c_char_p
         lib.mc_last_error.argtypes = []
@@ -415,3 +431,80 @@ def ws_warm_state(out: torch.Tensor, a_x: torch.Tensor, c: float = 0.0) -> torch
     _check(lib.mc_ws_warm_state(context(dev), ctypes.byref(_grid((H, W))), op, ap, float(c),
                                 ctypes.c_void_p(z0.data_ptr()), _stream(dev)))
     return z0
+
+
+# ---- multi-label energies by alpha-expansion ----------------------------------------
+
+def _ml_args(data, lam, labels):
+    if data.dim() != 3:
+        raise ValueError("data must be (n_labels, H, W)")
+    L, H, W = (int(x) for x in data.shape)
+    dp = _dev_f32(data, (L, H, W), "data")
+    if len(lam) != 2:
+        raise ValueError("lam must hold two arrays (along W, along H)")
+    lp = (ctypes.c_void_p * 2)(_dev_f32(lam[0], (H, W), "lam[0]").value, _dev_f32(lam[1], (H, W), "lam[1]").value)
+    if (not isinstance(labels, torch.Tensor) or labels.device != data.device or labels.dtype != torch.int32
+            or tuple(labels.shape) != (H, W) or not labels.is_contiguous()):
+        raise ValueError("labels must be a contiguous int32 device tensor of shape (H, W)")
+    dev = data.device.index if data.device.index is not None else torch.cuda.current_device()
+    return L, H, W, dp, lp, dev
+
+
+def expansion_problem(data, lam, labels, alpha, kind=V_TRUNC_LINEAR, trunc=2.0):
+    """Binary problem (w, [a_x, a_y]) of the expansion move of `alpha` (mc_expansion_problem)."""
+    lib = load_library()
+    L, H, W, dp, lp, dev = _ml_args(data, lam, labels)
+    w = torch.empty((H, W), dtype=torch.float32, device=data.device)
+    a = [torch.empty((H, W), dtype=torch.float32, device=data.device) for _ in range(2)]
+    ap = (ctypes.c_void_p * 2)(a[0].data_ptr(), a[1].data_ptr())
+    _check(lib.mc_expansion_problem(context(dev), ctypes.byref(_grid((H, W))), L, dp, ctypes.cast(lp, ctypes.c_void_p),
+                                    int(kind), float(trunc), ctypes.c_void_p(labels.data_ptr()), int(alpha),
+                                    ctypes.c_void_p(w.data_ptr()), ctypes.cast(ap, ctypes.c_void_p), _stream(dev)))
+    return w, a
+
+
+def ml_energy(data, lam, labels, kind=V_TRUNC_LINEAR, trunc=2.0) -> float:
+    """Multi-label energy E(f) in FP64 on the device (mc_ml_energy)."""
+    lib = load_library()
+    L, H, W, dp, lp, dev = _ml_args(data, lam, labels)
+    e = ctypes.c_double(0)
+    _check(lib.mc_ml_energy(context(dev), ctypes.byref(_grid((H, W))), L, dp, ctypes.cast(lp, ctypes.c_void_p),
+                            int(kind), float(trunc), ctypes.c_void_p(labels.data_ptr()), ctypes.byref(e),
+                            _stream(dev)))
+    return e.value
+
+
+@dataclass
+class MLResult:
+    status: int
+    cycles: int
+    moves: int
+    accepted: int
+    uncertified: int
+    dr_iters: int
+    energy0: float
+    energy: float
+    ms: float
+
+    @property
+    def converged(self):
+        return self.status == MC_OK
+
+
+def alpha_expansion(data, lam, labels, kind=V_TRUNC_LINEAR, trunc=2.0, max_cycles=50, max_iters=2000,
+                    check_every=4, gap_tol=1e-3, validate=False, warm=False) -> MLResult:
+    """Alpha-expansion from `labels`, in place (mc_alpha_expansion); every move
+    is an exact mc_tv_solve, started from the same label's previous move when
+    `warm`."""
+    lib = load_library()
+    L, H, W, dp, lp, dev = _ml_args(data, lam, labels)
+    st = MLStats()
+    o = make_opts(max_iters, check_every, gap_tol, VARIANT_AUTO, 1e-3, validate, False)
+    if warm:
+        o.flags |= MC_WARM_MOVES
+    rc = lib.mc_alpha_expansion(context(dev), ctypes.byref(_grid((H, W))), L, dp, ctypes.cast(lp, ctypes.c_void_p),
+                                int(kind), float(trunc), ctypes.c_void_p(labels.data_ptr()), int(max_cycles),
+                                ctypes.byref(st), ctypes.byref(o), _stream(dev))
+    _check(rc, allow_not_converged=True)
+    return MLResult(st.status, st.cycles, st.moves, st.accepted, st.uncertified, st.dr_iters, st.energy0,
+                    st.energy, st.ms)

@@ -32,7 +32,8 @@ def test_header_declares_boundary():
     names = declared_functions()
     for n in ("mc_tv_solve", "mc_tv_prox_chains", "mc_cut_energy", "mc_tv_solve_batched", "mc_ctx_create",
               "mc_ctx_destroy", "mc_status_string", "mc_last_error", "mc_opts_default", "mc_ws_param_count",
-              "mc_ws_forward", "mc_ws_backward", "mc_ws_adam_step", "mc_ws_warm_state"):
+              "mc_ws_forward", "mc_ws_backward", "mc_ws_adam_step", "mc_ws_warm_state",
+              "mc_expansion_problem", "mc_ml_energy", "mc_alpha_expansion"):
         assert n in names
 
 
@@ -66,6 +67,10 @@ def test_host_only_calls(libpath):
     assert lib.mc_ws_forward(None, None, 1, 1, 1, None, None, None, None, None) == -1
     assert lib.mc_ws_adam_step(None, None, None, None, None, 1, 0.1, 0.9, 0.999, 1e-8, None) == -1
     assert lib.mc_ws_warm_state(None, None, None, None, 0.0, None, None) == -1
+    # alpha-expansion entry points reject a null context before any device work
+    assert lib.mc_expansion_problem(None, None, 2, None, None, 0, 0.0, None, 0, None, None, None) == -1
+    assert lib.mc_ml_energy(None, None, 2, None, None, 0, 0.0, None, None, None) == -1
+    assert lib.mc_alpha_expansion(None, None, 2, None, None, 0, 0.0, None, 1, None, None, None) == -1
 
 
 def test_struct_layouts_match_header():
@@ -74,3 +79,6 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(mc.Opts) == 48
     assert ctypes.sizeof(mc.Stats) == 72
     assert mc.Stats.ms.offset == 44 and mc.Opts.flags.offset == 24
+    assert ctypes.sizeof(mc.MLStats) == 56
+    assert (mc.MLStats.dr_iters.offset, mc.MLStats.energy0.offset, mc.MLStats.energy.offset,
+            mc.MLStats.ms.offset) == (24, 32, 40, 48)
