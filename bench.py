@@ -263,10 +263,19 @@ def alpha_expansion_section(seed=6000, shape=(288, 384), n_labels=16, repeats=3)
         res = mc.alpha_expansion(dt, lt, labels, mc.V_TRUNC_LINEAR, 2.0)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
+    # the same with the overlapping-piece sweeps (one run)
+    lp = zeros.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mc.alpha_expansion(dt, lt, lp, mc.V_TRUNC_LINEAR, 2.0, whole_chains=False)
+    torch.cuda.synchronize()
+    t_piece = time.perf_counter() - t0
     return {
         "workload": "stereo-like %dx%d, %d labels, truncated linear T=2, seed %d" % (shape[1], shape[0], n_labels,
                                                                                       seed),
+        "sweeps": "whole chains (one lane per chain)",
         "time_ms": 1e3 * float(np.median(times)),
+        "time_ms_piece_sweeps": 1e3 * t_piece,
         "cycles": res.cycles,
         "moves": res.moves,
         "accepted": res.accepted,

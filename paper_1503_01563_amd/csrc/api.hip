@@ -532,6 +532,7 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     if (opts_in) o = *opts_in; else mc_opts_default(&o);
     if (o.max_iters < 1 || o.check_every < 1) return fail(MC_ERR_INVALID_ARG, "max_iters and check_every must be >= 1");
     if (!(o.tau0 >= 0.f)) return fail(MC_ERR_INVALID_ARG, "tau0 must be >= 0");
+    g.whole = (o.flags & MC_WHOLE_CHAINS) ? 1 : 0;
     if (grid->conn == 8) {
         if (g.ndim != 2) return fail(MC_ERR_INVALID_ARG, "8-connected grids are 2D");
         if (o.variant == MC_VARIANT_TWO_SET) return fail(MC_ERR_INVALID_ARG, "8-connected grids use the product space");

@@ -13,6 +13,7 @@ struct Geo {
     int D, H, W;
     int n;
     int ndim;
+    int whole = 0;  // sweeps: every chain in one piece, one lane per chain (no overlap, no restarts)
 };
 
 __host__ __device__ inline int geo_extent(const Geo& g, int axis)

@@ -426,6 +426,42 @@ __device__ __forceinline__ int xcd_item(int b, int n)
     return ((j / kXcdRun) * kXcds + x) * kXcdRun + j % kXcdRun;
 }
 
+// Whole chains: one lane per chain runs a single exact scan from the chain
+// start, where the dual is 0, so there is no bracket and no restart; the fill
+// trails the scan and writes each output through the mode.  Values come from
+// global memory (a lane walks its own chain: rows share cache lines, columns
+// are coalesced across lanes).  When the chain proxes have long constant
+// segments, the brackets of the piece scheme do not close and its lanes scan
+// back to the chain start anyway, many lanes per chain; here each chain is
+// scanned once.
+template <class M, bool kExact>
+__global__ void __launch_bounds__(kLanes) k_sweep_whole(Geo g, int axis, M mode)
+{
+    const int c = blockIdx.x * kLanes + threadIdx.x;
+    const int m = geo_extent(g, axis);
+    const bool valid = c < geo_nchains(g, axis);
+    const Chain ch = chain_of(g, axis, valid ? c : 0);
+    auto at = [&](int q) -> RingVals<2> {
+        const int i = ch.base + q * ch.stride;
+        return {{mode.v_at(i), mode.a_at(i)}};
+    };
+    auto emit = [&](int q, auto cv, auto pr, bool last, bool on) {
+        if (!on) return;
+        const int i = ch.base + q * ch.stride;
+        float pd = 0.f;
+        if constexpr (kExact) pd = last ? 0.f : clip_dual(pr, mode.a_at(i));
+        mode.store(i, mode.pre(i), (float)cv, pd);
+    };
+    auto no_weight_before = [](int) { return 0.f; };  // never read: the scan starts at the chain start
+    PieceLane<2, kExact> pl;
+    pl.begin(valid, m, 0, m, 1, no_weight_before);
+    while (__any(pl.busy())) {
+        const RingVals<2> rf = at(pl.fill_pos(0)), rl = at(pl.l_pos(0));
+        pl.fill(rf, emit);
+        pl.step_l(rl);
+    }
+}
+
 template <class M, bool kRows, bool kExact>
 __global__ void __launch_bounds__(kLanes) k_sweep(Geo g, int axis, M mode, PieceCfg cfg)
 {
@@ -471,6 +507,12 @@ hipError_t launch_mode_x(const Geo& g, int axis, const M& mode, const PieceCfg& 
 template <class M>
 hipError_t launch_mode(const Geo& g, int axis, const M& mode, bool duals, hipStream_t s)
 {
+    if (g.whole) {
+        const dim3 grid((geo_nchains(g, axis) + kLanes - 1) / kLanes), block(kLanes);
+        if (duals) hipLaunchKernelGGL((k_sweep_whole<M, true>), grid, block, 0, s, g, axis, mode);
+        else hipLaunchKernelGGL((k_sweep_whole<M, false>), grid, block, 0, s, g, axis, mode);
+        return hipGetLastError();
+    }
     const PieceCfg cfg = piece_config(g, axis, kDefaultItems, 0);
     return duals ? launch_mode_x<M, true>(g, axis, mode, cfg, s)
                  : launch_mode_x<M, false>(g, axis, mode, cfg, s);
@@ -591,6 +633,10 @@ hipError_t launch_drp_sweeps(const Geo& g, int nfam, const float* z, const float
     if (nfam == 1) return launch_mode(g, 0, m0, p != nullptr, s);
     if (nfam != 2) return hipErrorInvalidValue;
     ModeSweepP m1{z + n, a[1], q + n, p ? p + n : nullptr};
+    if (g.whole) {
+        const hipError_t e = launch_mode(g, 0, m0, p != nullptr, s);
+        return e != hipSuccess ? e : launch_mode(g, 1, m1, p != nullptr, s);
+    }
     PieceCfg c0 = piece_config(g, 0, kDefaultItems, 0), c1 = piece_config(g, 1, kDefaultItems, 0);
     {
         // one launch holds both families: decide latency mode on its total

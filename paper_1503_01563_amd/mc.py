@@ -28,6 +28,7 @@ MC_NOT_CONVERGED = 1
 MC_VALIDATE = 1
 MC_PROFILE = 2
 MC_WARM_MOVES = 4
+MC_WHOLE_CHAINS = 8
 VARIANT_AUTO, VARIANT_TWO_SET, VARIANT_PRODUCT = 0, 1, 2
 VARIANT_BCD, VARIANT_AP, VARIANT_FISTA = 3, 4, 5
 V_POTTS, V_TRUNC_LINEAR = 0, 1
@@ -207,7 +208,7 @@ class SolveResult:
 
 
 def make_opts(max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
-              validate=False, profile=False):
+              validate=False, profile=False, whole_chains=False):
     o = Opts()
     load_library().mc_opts_default(ctypes.byref(o))
     o.max_iters = int(max_iters)
@@ -215,14 +216,15 @@ def make_opts(max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, 
     o.gap_tol = float(gap_tol)
     o.variant = int(variant)
     o.tau0 = float(tau0)
-    o.flags = (MC_VALIDATE if validate else 0) | (MC_PROFILE if profile else 0)
+    o.flags = (MC_VALIDATE if validate else 0) | (MC_PROFILE if profile else 0) | \
+        (MC_WHOLE_CHAINS if whole_chains else 0)
     return o
 
 
 def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tensor] = None,
              max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
              validate=False, return_x=True, return_z=False, labels_out=None,
-             profile=False) -> SolveResult:
+             profile=False, whole_chains=False) -> SolveResult:
     """Minimum cut of one grid by mc_tv_solve."""
     lib = load_library()
     shape = tuple(w.shape)
@@ -244,7 +246,7 @@ def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tens
     x = torch.empty(shape, dtype=torch.float32, device=w.device) if return_x else None
     z = torch.empty(nz, dtype=torch.float32, device=w.device) if return_z else None
     st = Stats()
-    o = make_opts(max_iters, check_every, gap_tol, variant, tau0, validate, profile)
+    o = make_opts(max_iters, check_every, gap_tol, variant, tau0, validate, profile, whole_chains)
     rc = lib.mc_tv_solve(context(dev), ctypes.byref(_grid(shape, conn)), wp,
                          ctypes.cast(ap, ctypes.c_void_p), z0p,
                          ctypes.c_void_p(x.data_ptr()) if x is not None else None,
@@ -492,14 +494,16 @@ class MLResult:
 
 
 def alpha_expansion(data, lam, labels, kind=V_TRUNC_LINEAR, trunc=2.0, max_cycles=50, max_iters=2000,
-                    check_every=4, gap_tol=1e-3, validate=False, warm=False) -> MLResult:
+                    check_every=4, gap_tol=1e-3, validate=False, warm=False, whole_chains=True) -> MLResult:
     """Alpha-expansion from `labels`, in place (mc_alpha_expansion); every move
     is an exact mc_tv_solve, started from the same label's previous move when
-    `warm`."""
+    `warm`, with whole-chain sweeps when `whole_chains` (the default: move
+    problems are flat where the labels agree, their chain proxes have long
+    constant segments)."""
     lib = load_library()
     L, H, W, dp, lp, dev = _ml_args(data, lam, labels)
     st = MLStats()
-    o = make_opts(max_iters, check_every, gap_tol, VARIANT_AUTO, 1e-3, validate, False)
+    o = make_opts(max_iters, check_every, gap_tol, VARIANT_AUTO, 1e-3, validate, False, whole_chains)
     if warm:
         o.flags |= MC_WARM_MOVES
     rc = lib.mc_alpha_expansion(context(dev), ctypes.byref(_grid((H, W))), L, dp, ctypes.cast(lp, ctypes.c_void_p),

@@ -1,0 +1,75 @@
+"""Whole-chain sweeps (MC_WHOLE_CHAINS: one lane per chain, a single exact
+scan from the chain start) against the FP64 reference: splitting iterates
+after 1, 3 and 20 iterations, exact cuts against max-flow, and the
+alpha-expansion moves, whose flat chains are what the option is for."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import multilabel as ml
+from paper_1503_01563_amd import gen
+
+pytestmark = pytest.mark.gpu
+REL_TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1503_01563_amd import mc
+    mc.load_library()
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+
+
+@pytest.mark.parametrize("shape,variant", [((37, 53), 1), ((37, 53), 2), ((6, 17, 23), 2), ((1, 70), 1),
+                                           ((70, 1), 1)])
+@pytest.mark.parametrize("iters", [1, 3, 20])
+def test_iterates_match_reference(dev, shape, variant, iters):
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid(shape, 900 + iters)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=iters, gap_tol=0.0, variant=variant,
+                      whole_chains=True)
+    ref = oracle.dr_solve(w, a, variant=variant - 1, max_iters=iters, gap_tol=0.0)
+    x = res.x.cpu().numpy()
+    scale = max(1.0, np.abs(ref["x"]).max())
+    assert np.abs(x - ref["x"]).max() / scale <= REL_TOL
+
+
+@pytest.mark.parametrize("seed", range(1000, 1006))
+def test_exact_against_maxflow(dev, seed):
+    from paper_1503_01563_amd import mc
+    w, a = gen.config_small(seed)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=2000, check_every=2, whole_chains=True)
+    assert res.converged
+    assert res.energy == oracle.mincut(w, a, "dinic")[0]
+
+
+def test_volume_and_image_exact(dev):
+    from paper_1503_01563_amd import mc
+    w, a = gen.ellipse_grid((12, 40, 56), 3100, lam=1.5)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=3000, check_every=4, whole_chains=True)
+    assert res.converged and res.energy == oracle.mincut(w, a, "dinic")[0]
+    w, a = gen.config_image2d(2001, (256, 256))
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=3000, check_every=4, whole_chains=True)
+    assert res.converged and res.energy == oracle.mincut(w, a, "dinic")[0]
+
+
+def test_alpha_expansion_with_whole_chains(dev):
+    import torch
+    from paper_1503_01563_amd import mc
+    data, lam, _ = gen.stereo_labels((96, 128), 6800, n_labels=10)
+    labels = torch.zeros((96, 128), dtype=torch.int32, device=dev)
+    res = mc.alpha_expansion(T(data, dev), [T(x, dev) for x in lam], labels, 1, 2.0, whole_chains=True)
+    assert res.converged and res.uncertified == 0
+    f = labels.cpu().numpy()
+    assert res.energy == ml.energy(data, lam, 1, 2.0, f)
+    for alpha in range(10):
+        w, a = ml.expansion_problem(data, lam, 1, 2.0, f, alpha)
+        assert oracle.mincut(w, a)[0] >= 0
