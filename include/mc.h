@@ -71,6 +71,12 @@ extern "C" {
                                     columns): sweep every chain with one lane from its start instead of
                                     in overlapping pieces; faster when the chain proxes have long
                                     constant segments, slower otherwise */
+#define MC_PIECE_CHAINS 16u      /* mc_tv_solve: always sweep in overlapping pieces.  With neither this
+                                    nor MC_WHOLE_CHAINS, the splitting of 4- and 6-connected grids
+                                    (variants AUTO, TWO_SET, PRODUCT) runs its first sweeps in pieces,
+                                    counts the lanes whose bracket did not close, and sweeps whole
+                                    chains for the rest of the solve when they are 1 in 10 or more
+                                    (one extra stream synchronisation); other solvers use pieces */
 
 /* mc_opts.variant */
 #define MC_VARIANT_AUTO 0        /* two-set form for 2D, product space for 3D */
@@ -99,7 +105,7 @@ typedef struct {
     float tau0;           /* labels S_tau = {x > tau} for the ladder tau = tau0 * (1, 1e-1, 1e-2,
                              1e-3, 0, -1e-3, -1e-2, -1e-1, -1); the first of least energy
                              is returned (default 1e-3) */
-    uint32_t flags;       /* MC_VALIDATE | MC_PROFILE | MC_WARM_MOVES | MC_WHOLE_CHAINS */
+    uint32_t flags;       /* MC_VALIDATE | MC_PROFILE | MC_WARM_MOVES | MC_WHOLE_CHAINS | MC_PIECE_CHAINS */
     int32_t reserved[4];  /* reserved[0]: work items per sweep launch of batched solves (0 = tuned) */
 } mc_opts;
 
@@ -116,7 +122,7 @@ typedef struct {
     int32_t sweep_launches; /* number of chain-sweep launches (counted with or without MC_PROFILE) */
     int32_t checks;       /* certificate evaluations performed */
     int32_t items;        /* batched solves: work items per sweep launch used */
-    int32_t reserved2;
+    int32_t whole_chains; /* mc_tv_solve splitting: 1 when the sweeps ended as whole chains */
 } mc_stats;
 
 /* Fill `o` with the defaults listed above. */

@@ -447,6 +447,8 @@ int mc_ctx_create(mc_ctx** out, int device)
     if (hipMalloc(&c->partials, sizeof(double) * kReduceBlocks * kCertValues) != hipSuccess ||
         hipMalloc(&c->dout, sizeof(double) * kCertValues) != hipSuccess ||
         hipHostMalloc(&c->hout, sizeof(double) * kCertValues, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc(&c->scnt, 2 * sizeof(int)) != hipSuccess ||
+        hipHostMalloc(&c->scnt_h, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess ||
         hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
         hipStreamCreateWithFlags(&c->bstream, hipStreamNonBlocking) != hipSuccess) {
         (void)hipGetLastError();
@@ -467,6 +469,8 @@ int mc_ctx_destroy(mc_ctx* c)
     (void)hipFree(c->partials);
     (void)hipFree(c->dout);
     if (c->hout) (void)hipHostFree(c->hout);
+    (void)hipFree(c->scnt);
+    if (c->scnt_h) (void)hipHostFree(c->scnt_h);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
@@ -532,6 +536,8 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     if (opts_in) o = *opts_in; else mc_opts_default(&o);
     if (o.max_iters < 1 || o.check_every < 1) return fail(MC_ERR_INVALID_ARG, "max_iters and check_every must be >= 1");
     if (!(o.tau0 >= 0.f)) return fail(MC_ERR_INVALID_ARG, "tau0 must be >= 0");
+    if ((o.flags & MC_WHOLE_CHAINS) && (o.flags & MC_PIECE_CHAINS))
+        return fail(MC_ERR_INVALID_ARG, "MC_WHOLE_CHAINS and MC_PIECE_CHAINS exclude each other");
     g.whole = (o.flags & MC_WHOLE_CHAINS) ? 1 : 0;
     if (grid->conn == 8) {
         if (g.ndim != 2) return fail(MC_ERR_INVALID_ARG, "8-connected grids are 2D");
@@ -575,6 +581,12 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     CheckState st;
     int it = 0;
     bool converged = false;
+    // neither sweep kind forced: the first sweeps run as pieces and count restarts
+    bool probing = !(o.flags & (MC_WHOLE_CHAINS | MC_PIECE_CHAINS));
+    if (probing) {
+        MC_HIP(hipMemsetAsync(c->scnt, 0, 2 * sizeof(int), s));
+        g.restarts = c->scnt;
+    }
     float* zc = c->z;   // current state
     float* zn = c->z2;  // next state
     while (it < o.max_iters) {
@@ -613,6 +625,17 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
         float* zt = zc;
         zc = zn;
         zn = zt;
+        if (probing && tm.launches > 0) {
+            // the first sweeps of the solve ran as pieces and counted their
+            // restarts: when at least 1 in 10 lanes failed its bracket the
+            // chain proxes have long constant segments, and the rest of the
+            // solve sweeps whole chains
+            MC_HIP(hipMemcpyAsync(c->scnt_h, c->scnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+            MC_HIP(hipStreamSynchronize(s));
+            probing = false;
+            g.restarts = nullptr;
+            if (c->scnt_h[0] > 0 && 10ll * c->scnt_h[0] >= (long long)c->scnt_h[1]) g.whole = 1;
+        }
         if (!check) continue;
         bool done = false;
         if ((rc = run_check(c, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
@@ -621,7 +644,9 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
             break;
         }
     }
-    return finish_solve(c, g, zc, nz, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
+    rc = finish_solve(c, g, zc, nz, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
+    stats->whole_chains = g.whole;
+    return rc;
 }
 
 }  // extern "C"

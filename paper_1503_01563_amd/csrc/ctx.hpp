@@ -23,6 +23,8 @@ struct mc_ctx {
     double* dout = nullptr;      // kCertValues doubles
     double* hout = nullptr;      // kCertValues doubles, pinned host
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    int* scnt = nullptr;     // 2 ints: restarted / run lanes of the probe sweep
+    int* scnt_h = nullptr;   // 2 ints, pinned host
     std::vector<hipEvent_t> prof_ev;  // MC_PROFILE: start/stop pairs of sweep launches
 
     // batched solves

@@ -14,6 +14,7 @@ struct Geo {
     int n;
     int ndim;
     int whole = 0;  // sweeps: every chain in one piece, one lane per chain (no overlap, no restarts)
+    int* restarts = nullptr;  // piece sweeps add {lanes that restarted, lanes run} here (null: no count)
 };
 
 __host__ __device__ inline int geo_extent(const Geo& g, int axis)

@@ -337,7 +337,8 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     };
     constexpr int kGrow = 8;
     PieceLane<2, kExact> pl;
-    pl.begin(valid, m, b0, b1, cfg.overlap > 0 ? cfg.overlap : 1, a_before);
+    const int W0 = cfg.overlap > 0 ? cfg.overlap : 1;
+    pl.begin(valid, m, b0, b1, W0, a_before);
     while (__any(pl.busy())) {
         // some lane's scan is about to read past the window: stage the next block
         if (hi < hi_cap && __any(pl.scanning && pl.L.k >= hi)) {
@@ -363,6 +364,16 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
         }
     }
     wave_fence();
+    if (g.restarts) {
+        // lanes whose bracket did not close (they restarted further back); one
+        // vector atomic per counter from lane 0
+        const int nr = __popcll(__ballot(valid && pl.W != W0));
+        const int nv = __popcll(__ballot(valid));
+        if (lane == 0) {
+            atomicAdd(g.restarts, nr);
+            atomicAdd(g.restarts + 1, nv);
+        }
+    }
 
     // store
     if (kRows) {

@@ -29,6 +29,7 @@ MC_VALIDATE = 1
 MC_PROFILE = 2
 MC_WARM_MOVES = 4
 MC_WHOLE_CHAINS = 8
+MC_PIECE_CHAINS = 16
 VARIANT_AUTO, VARIANT_TWO_SET, VARIANT_PRODUCT = 0, 1, 2
 VARIANT_BCD, VARIANT_AP, VARIANT_FISTA = 3, 4, 5
 V_POTTS, V_TRUNC_LINEAR = 0, 1
@@ -58,7 +59,7 @@ class Stats(ctypes.Structure):
                 ("lower_bound", ctypes.c_double), ("tv_gap", ctypes.c_double),
                 ("tau_used", ctypes.c_float), ("ms", ctypes.c_float),
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
-                ("checks", ctypes.c_int32), ("items", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("checks", ctypes.c_int32), ("items", ctypes.c_int32), ("whole_chains", ctypes.c_int32)]
 
 
 class MLStats(ctypes.Structure):
@@ -201,6 +202,7 @@ class SolveResult:
     sweep_ms: float = 0.0
     sweep_launches: int = 0
     checks: int = 0
+    whole_chains: int = 0
 
     @property
     def converged(self):
@@ -208,7 +210,9 @@ class SolveResult:
 
 
 def make_opts(max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
-              validate=False, profile=False, whole_chains=False):
+              validate=False, profile=False, whole_chains=None):
+    """whole_chains: None = chosen by the solver from its first sweeps, True =
+    whole-chain sweeps, False = overlapping pieces."""
     o = Opts()
     load_library().mc_opts_default(ctypes.byref(o))
     o.max_iters = int(max_iters)
@@ -216,15 +220,16 @@ def make_opts(max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, 
     o.gap_tol = float(gap_tol)
     o.variant = int(variant)
     o.tau0 = float(tau0)
-    o.flags = (MC_VALIDATE if validate else 0) | (MC_PROFILE if profile else 0) | \
-        (MC_WHOLE_CHAINS if whole_chains else 0)
+    o.flags = (MC_VALIDATE if validate else 0) | (MC_PROFILE if profile else 0)
+    if whole_chains is not None:
+        o.flags |= MC_WHOLE_CHAINS if whole_chains else MC_PIECE_CHAINS
     return o
 
 
 def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tensor] = None,
              max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
              validate=False, return_x=True, return_z=False, labels_out=None,
-             profile=False, whole_chains=False) -> SolveResult:
+             profile=False, whole_chains=None) -> SolveResult:
     """Minimum cut of one grid by mc_tv_solve."""
     lib = load_library()
     shape = tuple(w.shape)
@@ -256,7 +261,7 @@ def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tens
     _check(rc, allow_not_converged=True)
     return SolveResult(labels, x, z, st.status, st.iters, st.cert_gap, st.energy,
                        st.lower_bound, st.tau_used, st.ms, st.tv_gap, st.sweep_ms,
-                       st.sweep_launches, st.checks)
+                       st.sweep_launches, st.checks, st.whole_chains)
 
 
 def tv_prox_chains(v: torch.Tensor, a_axis: torch.Tensor, axis: int, return_p=False,

@@ -73,3 +73,22 @@ def test_alpha_expansion_with_whole_chains(dev):
     for alpha in range(10):
         w, a = ml.expansion_problem(data, lam, 1, 2.0, f, alpha)
         assert oracle.mincut(w, a)[0] >= 0
+
+
+def test_automatic_choice(dev):
+    """With neither kind forced the solver sweeps whole chains on flat move
+    problems and keeps pieces on noisy grids; both stay exact."""
+    from paper_1503_01563_amd import mc
+    data, lam, _ = gen.stereo_labels((96, 128), 6900, n_labels=8)
+    w, a = ml.expansion_problem(data, lam, 1, 2.0, np.zeros((96, 128), np.int64), 1)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=3000, check_every=4)
+    assert res.converged and res.whole_chains == 1
+    assert res.energy == oracle.mincut(w, a)[0]
+    w, a = gen.config_image2d(2002, (256, 256))
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=3000, check_every=4)
+    assert res.converged and res.whole_chains == 0
+    assert res.energy == oracle.mincut(w, a, "dinic")[0]
+    forced = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=3000, check_every=4, whole_chains=True)
+    assert forced.whole_chains == 1 and forced.energy == res.energy
+    pieces = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=3000, check_every=4, whole_chains=False)
+    assert pieces.whole_chains == 0 and pieces.energy == res.energy
