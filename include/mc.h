@@ -147,6 +147,11 @@ int mc_ctx_destroy(mc_ctx *ctx);
  *   labels_out [n] uint8, 1 = in S.
  *   z_out      nullable: final state, same size as z0.
  *   stats      host, required.
+ * Sweeps.  Each chain prox runs as overlapping pieces, many lanes per chain,
+ * or as whole chains, one lane per chain (see MC_WHOLE_CHAINS and
+ * MC_PIECE_CHAINS).  Unless forced, the splitting of 4- and 6-connected grids
+ * picks whole chains after its first sweeps when those show long constant
+ * segments; stats->whole_chains tells which kind ran last.
  * Returns MC_OK when cert < gap_tol (the labels are then a minimum cut
  * whenever all energies are multiples of a granularity g > gap_tol, e.g.
  * integer or 2^-8-dyadic data), MC_NOT_CONVERGED at max_iters, or an error.
