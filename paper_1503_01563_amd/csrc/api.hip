@@ -200,6 +200,8 @@ int finish_solve(mc_ctx* c, const Geo& g, const float* state, size_t nstate, flo
     stats->sweep_ms = tm.ms;
     stats->sweep_launches = tm.launches;
     stats->checks = st.checks;
+    stats->items = 0;
+    stats->whole_chains = g.whole;
     return stats->status;
 }
 
@@ -644,9 +646,7 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
             break;
         }
     }
-    rc = finish_solve(c, g, zc, nz, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
-    stats->whole_chains = g.whole;
-    return rc;
+    return finish_solve(c, g, zc, nz, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
 }
 
 }  // extern "C"

@@ -92,3 +92,23 @@ def test_automatic_choice(dev):
     assert forced.whole_chains == 1 and forced.energy == res.energy
     pieces = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=3000, check_every=4, whole_chains=False)
     assert pieces.whole_chains == 0 and pieces.energy == res.energy
+
+
+@pytest.mark.parametrize("variant", ["bcd", "ap", "fista"])
+def test_other_outer_iterations_with_whole_chains(dev, variant):
+    from paper_1503_01563_amd import mc
+    var = {"bcd": mc.VARIANT_BCD, "ap": mc.VARIANT_AP, "fista": mc.VARIANT_FISTA}[variant]
+    w, a = gen.iid_grid((40, 48), 5100)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=20000, check_every=2, variant=var,
+                      whole_chains=True)
+    assert res.converged and res.whole_chains == 1
+    assert res.energy == oracle.mincut(w, a, "dinic")[0]
+
+
+def test_grid8_with_whole_chains(dev):
+    from oracle import grid8 as G8
+    from paper_1503_01563_amd import mc
+    w, a = gen.ellipse_grid8((64, 80), 5200)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=5000, check_every=2, whole_chains=True)
+    assert res.converged
+    assert res.energy == G8.mincut(w, a)[0]
