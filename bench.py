@@ -204,6 +204,7 @@ def main():
         out["grid8"] = grid8_section(args.seed, shape)
     if args.multilabel:
         out["alpha_expansion"] = alpha_expansion_section()
+    out["mixed_outer_loop"] = mixed_outer_loop_section(args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a, last.energy, args.cpu_seconds)
     print(json.dumps(out))
@@ -286,6 +287,35 @@ def alpha_expansion_section(seed=6000, shape=(288, 384), n_labels=16, repeats=3)
         "local_minimum": res.converged,
         "label_error_vs_truth": float((labels.cpu().numpy() != true).mean()),
     }
+
+
+def mixed_outer_loop_section(seed=2000, repeats=3):
+    """Time to the exact cut of MC_VARIANT_BCD_DR (16 BCD iterations, then the
+    splitting from BCD's dual blocks) beside the plain splitting, on the bench
+    image and on an iid integer grid."""
+    import numpy as np
+    import torch
+
+    from paper_1503_01563_amd import gen, mc
+    dev = torch.device("cuda:0")
+    out = {}
+    for name, (w, a) in (("image2d_1024", gen.config_image2d(seed)), ("iid_512", gen.config_warm(130000))):
+        wt = torch.from_numpy(w).to(dev)
+        at = [torch.from_numpy(x).to(dev) for x in a]
+        row = {}
+        for vname, var in (("splitting", mc.VARIANT_AUTO), ("bcd_then_splitting", mc.VARIANT_BCD_DR)):
+            mc.tv_solve(wt, at, max_iters=6000, check_every=4, variant=var)
+            times, res = [], None
+            for _ in range(repeats):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = mc.tv_solve(wt, at, max_iters=6000, check_every=4, variant=var)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            row[vname] = {"time_to_exact_cut_ms": 1e3 * float(np.median(times)), "iters": res.iters,
+                          "certified": res.converged, "energy": res.energy}
+        out[name] = row
+    return out
 
 
 def dual_reuse_section(frames=8, shape=(512, 512), frac=0.02):

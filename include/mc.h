@@ -88,6 +88,13 @@ extern "C" {
 #define MC_VARIANT_BCD 3         /* cyclic projections / block coordinate descent (Sec. 4.1) */
 #define MC_VARIANT_AP 4          /* alternating projections in the product space (Sec. 4.2) */
 #define MC_VARIANT_FISTA 5       /* FISTA on the smooth dual, step 1/r (Sec. 4.1) */
+/* Block coordinate descent for up to opts->reserved[1] iterations (0 = 16),
+ * then, unless it certified, the splitting of MC_VARIANT_AUTO started from its
+ * dual blocks y and primal x = -w - sum_j y_j (two-set form: z0 = x + y_rows;
+ * product space: z0_j = y_j + x / r).  BCD certifies within tens of iterations
+ * on image-like data and can stall elsewhere; the splitting always finishes.
+ * z0 and z_out must be NULL; stats add up both phases. */
+#define MC_VARIANT_BCD_DR 6
 
 typedef struct mc_ctx mc_ctx;
 
@@ -106,7 +113,8 @@ typedef struct {
                              1e-3, 0, -1e-3, -1e-2, -1e-1, -1); the first of least energy
                              is returned (default 1e-3) */
     uint32_t flags;       /* MC_VALIDATE | MC_PROFILE | MC_WARM_MOVES | MC_WHOLE_CHAINS | MC_PIECE_CHAINS */
-    int32_t reserved[4];  /* reserved[0]: work items per sweep launch of batched solves (0 = tuned) */
+    int32_t reserved[4];  /* reserved[0]: work items per sweep launch of batched solves (0 = tuned);
+                             reserved[1]: BCD iterations of MC_VARIANT_BCD_DR (0 = 16) */
 } mc_opts;
 
 typedef struct {

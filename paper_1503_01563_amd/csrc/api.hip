@@ -552,6 +552,48 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     }
     if (o.variant == MC_VARIANT_BCD || o.variant == MC_VARIANT_AP || o.variant == MC_VARIANT_FISTA)
         return solve_variant(c, g, w, a, z0, x_out, labels_out, z_out, stats, o, (hipStream_t)stream);
+    if (o.variant == MC_VARIANT_BCD_DR) {
+        if (z0 || z_out) return fail(MC_ERR_INVALID_ARG, "MC_VARIANT_BCD_DR takes no z0 / z_out");
+        const int k = o.reserved[1] > 0 ? o.reserved[1] : 16;
+        hipStream_t s = (hipStream_t)stream;
+        mc_opts ob = o;
+        ob.variant = MC_VARIANT_BCD;
+        ob.max_iters = k < o.max_iters ? k : o.max_iters;
+        mc_stats s1;
+        rc = solve_variant(c, g, w, a, nullptr, x_out, labels_out, nullptr, &s1, ob, s);
+        if (rc < 0 || rc == MC_OK || ob.max_iters == o.max_iters) {
+            *stats = s1;
+            return rc;
+        }
+        // the BCD blocks y (r n) and the primal x (n) stay in the variant
+        // workspace, which the splitting does not use; the start state goes
+        // to its third block
+        const int r = g.ndim;
+        const size_t n = (size_t)g.n;
+        float* Y = c->vbuf;
+        float* Z0 = c->vbuf + 2 * (size_t)r * n;
+        float* X = c->vbuf + 3 * (size_t)r * n;
+        if (r == 2) {
+            MC_HIP(launch_add(n, X, Y, Z0, s));  // z0 = x + y_rows
+        } else {
+            for (int j = 0; j < r; ++j) {        // z0_j = y_j + x / r
+                MC_HIP(launch_scale(n, 1.f / (float)r, X, Z0 + (size_t)j * n, s));
+                MC_HIP(launch_add(n, Z0 + (size_t)j * n, Y + (size_t)j * n, Z0 + (size_t)j * n, s));
+            }
+        }
+        mc_opts od = o;
+        od.variant = MC_VARIANT_AUTO;
+        od.max_iters = o.max_iters - ob.max_iters;
+        od.flags &= ~(uint32_t)MC_VALIDATE;  // checked by the first phase
+        rc = mc_tv_solve(c, grid, w, a, Z0, x_out, labels_out, nullptr, stats, &od, stream);
+        if (rc < 0) return rc;
+        stats->iters += s1.iters;
+        stats->ms += s1.ms;
+        stats->sweep_ms += s1.sweep_ms;
+        stats->sweep_launches += s1.sweep_launches;
+        stats->checks += s1.checks;
+        return rc;
+    }
     bool two_set;
     if (o.variant == MC_VARIANT_AUTO) two_set = g.ndim == 2;
     else if (o.variant == MC_VARIANT_TWO_SET) two_set = true;

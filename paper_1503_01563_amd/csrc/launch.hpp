@@ -113,6 +113,7 @@ hipError_t launch_add(size_t n, const float* x, const float* y, float* v, hipStr
 hipError_t launch_rsub(size_t n, const float* a, float* d, hipStream_t s);                   // d = a - d
 hipError_t launch_sub(size_t n, const float* a, float* d, hipStream_t s);                    // d = d - a
 hipError_t launch_diff(size_t n, const float* a, const float* b, float* d, hipStream_t s);    // d = a - b
+hipError_t launch_scale(size_t n, float f, const float* a, float* d, hipStream_t s);     // d = f a
 // AP: y_j = l_j - q_j, x = -w - sum y_j, l_j = y_j + x / r (cold: l_j = -w / r)
 hipError_t launch_ap_update(size_t n, int r, float* lam, const float* q, const float* w, bool cold, hipStream_t s);
 // FISTA: yt = y + beta (y - yp), xt = -w - sum yt_j, v_j = yt_j + xt / r

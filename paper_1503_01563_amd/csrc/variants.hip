@@ -57,6 +57,12 @@ __global__ void k_diff(size_t n, const float* __restrict__ a, const float* __res
     GRID_STRIDE(i, n) d[i] = a[i] - b[i];
 }
 
+// d <- f * a
+__global__ void k_scale(size_t n, float f, const float* __restrict__ a, float* __restrict__ d)
+{
+    GRID_STRIDE(i, n) d[i] = f * a[i];
+}
+
 template <int R>
 __global__ void k_ap_update(size_t n, float* __restrict__ lam, const float* __restrict__ q,
                             const float* __restrict__ w)
@@ -136,6 +142,12 @@ hipError_t launch_sub(size_t n, const float* a, float* d, hipStream_t s)
 hipError_t launch_diff(size_t n, const float* a, const float* b, float* d, hipStream_t s)
 {
     hipLaunchKernelGGL(k_diff, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, a, b, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(size_t n, float f, const float* a, float* d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, f, a, d);
     return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ MC_WHOLE_CHAINS = 8
 MC_PIECE_CHAINS = 16
 VARIANT_AUTO, VARIANT_TWO_SET, VARIANT_PRODUCT = 0, 1, 2
 VARIANT_BCD, VARIANT_AP, VARIANT_FISTA = 3, 4, 5
+VARIANT_BCD_DR = 6
 V_POTTS, V_TRUNC_LINEAR = 0, 1
 
 

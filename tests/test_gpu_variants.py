@@ -77,3 +77,30 @@ def test_iteration_comparison(dev):
                 assert res.energy == e_star, (cname, vname)
             line.append("%s %d it %.1f ms" % (vname, res.iters, res.ms))
         print("%s: %s" % (cname, "; ".join(line)))
+
+
+@pytest.mark.parametrize("case", ["image2d", "iid2d", "iid3d", "ellipsoid3d"])
+def test_bcd_then_splitting_is_exact(dev, case):
+    """MC_VARIANT_BCD_DR: BCD for 16 iterations, then the splitting from its
+    dual blocks; exact whichever phase certifies."""
+    from paper_1503_01563_amd import mc
+    if case == "image2d":
+        w, a = gen.config_image2d(2003, (192, 256))
+    elif case == "iid2d":
+        w, a = gen.iid_grid((96, 112), 4400)
+    elif case == "iid3d":
+        w, a = gen.iid_grid((10, 18, 22), 12)
+    else:
+        w, a = gen.ellipse_grid((16, 32, 32), 3100, lam=1.5)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=20000, check_every=2,
+                      variant=mc.VARIANT_BCD_DR)
+    assert res.converged, case
+    assert res.energy == oracle.mincut(w, a, "dinic")[0], case
+    print("bcd+dr %s: %d iterations" % (case, res.iters))
+
+
+def test_bcd_then_splitting_rejects_states(dev):
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid((8, 9), 2)
+    with pytest.raises(mc.McError):
+        mc.tv_solve(T(w, dev), [T(x, dev) for x in a], variant=mc.VARIANT_BCD_DR, return_z=True)
