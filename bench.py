@@ -75,6 +75,8 @@ def parse():
                     help="skip the 8-connected version of the workload")
     ap.add_argument("--no-multilabel", dest="multilabel", action="store_false",
                     help="skip the alpha-expansion (multi-label) section")
+    ap.add_argument("--no-mixed", dest="mixed", action="store_false",
+                    help="skip the section comparing the mixed BCD-then-splitting loop")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed steps, copy 256 MiB device to device (a reference "
                          "kernel for the HBM byte counters of a profiler run)")
@@ -204,7 +206,8 @@ def main():
         out["grid8"] = grid8_section(args.seed, shape)
     if args.multilabel:
         out["alpha_expansion"] = alpha_expansion_section()
-    out["mixed_outer_loop"] = mixed_outer_loop_section(args.seed)
+    if args.mixed:
+        out["mixed_outer_loop"] = mixed_outer_loop_section(args.seed)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a, last.energy, args.cpu_seconds)
     print(json.dumps(out))
