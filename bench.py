@@ -40,6 +40,8 @@ def sweep_sources_hash():
     for f in SWEEP_SOURCES:
         with open(os.path.join(ROOT, "paper_1503_01563_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, "paper_1503_01563_amd", "build.py"), "rb") as fh:  # compiler flags
+        h.update(fh.read())
     return h.hexdigest()[:16]
 
 

@@ -28,11 +28,15 @@ FLAGS = [
     "-I" + INCLUDE, "-I" + CSRC,
     "-Wall", "-Wno-unused-function",
 ]
+# per-source additions: the chain sweeps run one wave per SIMD at full-chip
+# sizes and spend a third of their cycles on dependency stalls; the ILP
+# scheduler interleaves the independent scans more (measured 2-5 % faster)
+EXTRA_FLAGS = {"sweeps.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC] + FLAGS + EXTRA_FLAGS.get(src, []) + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))
