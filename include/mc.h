@@ -55,7 +55,7 @@ extern "C" {
 /* status codes */
 #define MC_OK 0
 #define MC_NOT_CONVERGED 1       /* max_iters reached; outputs are the last iterate */
-#define MC_ERR_INVALID_ARG (-1)  /* null pointer, bad dims, n > 2^31-1, bad axis, bad opts */
+#define MC_ERR_INVALID_ARG (-1)  /* null pointer, bad dims, n > 2^31 - 2^24, bad axis, bad opts */
 #define MC_ERR_NEGATIVE_WEIGHT (-2) /* MC_VALIDATE only: some a < 0 (or non-zero on a last slice) */
 #define MC_ERR_NONFINITE (-3)    /* MC_VALIDATE only: NaN/Inf in w or a */
 #define MC_ERR_NOMEM (-4)        /* workspace allocation failed */

@@ -38,8 +38,8 @@ int make_geo(const mc_grid* grid, Geo* g)
     }
     if (D <= 0 || H <= 0 || W <= 0) return set_error(MC_ERR_INVALID_ARG, "dims must be positive");
     const int64_t n = D * H * W;
-    if (n > INT32_MAX || D > INT32_MAX || H > INT32_MAX || W > INT32_MAX)
-        return set_error(MC_ERR_INVALID_ARG, "grid has more than 2^31-1 nodes");
+    if (n > kMaxNodes || D > INT32_MAX || H > INT32_MAX || W > INT32_MAX)
+        return set_error(MC_ERR_INVALID_ARG, "grid has more than 2^31 - 2^24 nodes");
     if (W >= (1 << 30) || H >= (1 << 30) || D >= (1 << 30))
         return set_error(MC_ERR_INVALID_ARG, "chain length must be below 2^30");
     g->D = (int)D; g->H = (int)H; g->W = (int)W;
@@ -321,7 +321,7 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
     const size_t n = (size_t)g.n;
     const int H = g.H, W = g.W;
     const size_t nz = (size_t)2 * (H > 1 ? H - 1 : 0) * W;
-    if (nz > (size_t)INT32_MAX) return fail(MC_ERR_INVALID_ARG, "8-connected grid too large (2(H-1)W > 2^31-1)");
+    if (nz > (size_t)kMaxNodes) return fail(MC_ERR_INVALID_ARG, "8-connected grid too large (2(H-1)W > 2^31 - 2^24)");
     int rc;
     if ((rc = ensure_ws(c, n, R))) return rc;
     const size_t need = R * n + 4 * nz;

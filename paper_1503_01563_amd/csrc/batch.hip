@@ -177,7 +177,7 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
             return set_error(MC_ERR_INVALID_ARG, "batched grids are 4-connected");
         if (gr.ndim != 2 || gr.dims[0] <= 0 || gr.dims[1] <= 0)
             return set_error(MC_ERR_INVALID_ARG, "batched grids must be 2D with positive dims");
-        if (gr.dims[0] * gr.dims[1] > INT32_MAX || gr.dims[0] >= (1 << 30) || gr.dims[1] >= (1 << 30))
+        if (gr.dims[0] * gr.dims[1] > kMaxNodes || gr.dims[0] >= (1 << 30) || gr.dims[1] >= (1 << 30))
             return set_error(MC_ERR_INVALID_ARG, "grid too large");
         if (!w[gi] || !a[2 * gi] || !a[2 * gi + 1] || !labels[gi])
             return set_error(MC_ERR_INVALID_ARG, "null array for a grid");

@@ -645,7 +645,7 @@ int mc_ws_warm_state(mc_ctx* c, const mc_grid* grid, const float* out, const flo
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return mc::hip_error(e, "hipSetDevice");
     if (!grid || grid->ndim != 2) return mc::set_error(MC_ERR_INVALID_ARG, "warm state needs a 2D grid");
-    if (grid->dims[0] < 1 || grid->dims[1] < 1 || (double)grid->dims[0] * grid->dims[1] > 2147483647.0)
+    if (grid->dims[0] < 1 || grid->dims[1] < 1 || (double)grid->dims[0] * grid->dims[1] > (double)mc::kMaxNodes)
         return mc::set_error(MC_ERR_INVALID_ARG, "bad grid dims");
     if (!out || !a_x || !z0) return mc::set_error(MC_ERR_INVALID_ARG, "null array");
     const int H = (int)grid->dims[0], W = (int)grid->dims[1];

@@ -56,6 +56,11 @@ struct mc_ctx {
 
 namespace mc {
 
+// Largest node count (and n_labels * nodes) accepted: the kernels index with
+// int and step grid-stride loops by at most 2^20, so 2^24 of headroom below
+// 2^31 keeps every index and step in range.
+constexpr int64_t kMaxNodes = (int64_t(1) << 31) - (int64_t(1) << 24);
+
 int set_error(int code, const std::string& msg);
 
 // grid -> Geo with the checks every entry point shares (dims, size limits, conn)

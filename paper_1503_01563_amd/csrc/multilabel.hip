@@ -126,7 +126,7 @@ int check_ml(mc_ctx* c, const mc_grid* grid, int L, const float* data, const flo
     if (g->ndim != 2 || (grid->conn != 0 && grid->conn != 4))
         return set_error(MC_ERR_INVALID_ARG, "alpha-expansion needs a 2D 4-connected grid");
     if (L < 1) return set_error(MC_ERR_INVALID_ARG, "n_labels must be >= 1");
-    if ((int64_t)L * g->n > INT32_MAX) return set_error(MC_ERR_INVALID_ARG, "n_labels * H * W above 2^31-1");
+    if ((int64_t)L * g->n > kMaxNodes) return set_error(MC_ERR_INVALID_ARG, "n_labels * H * W above 2^31 - 2^24");
     if (!data || !lam || !lam[0] || !lam[1] || !labels) return set_error(MC_ERR_INVALID_ARG, "null argument");
     if (kind != MC_V_POTTS && kind != MC_V_TRUNC_LINEAR) return set_error(MC_ERR_INVALID_ARG, "unknown v_kind");
     if (kind == MC_V_TRUNC_LINEAR && !(trunc >= 0.f && isfinite(trunc)))

@@ -500,7 +500,8 @@ class MLResult:
 
 
 def alpha_expansion(data, lam, labels, kind=V_TRUNC_LINEAR, trunc=2.0, max_cycles=50, max_iters=2000,
-                    check_every=4, gap_tol=1e-3, validate=False, warm=False, whole_chains=True) -> MLResult:
+                    check_every=4, gap_tol=1e-3, validate=False, warm=False, whole_chains=True,
+                    variant=VARIANT_AUTO) -> MLResult:
     """Alpha-expansion from `labels`, in place (mc_alpha_expansion); every move
     is an exact mc_tv_solve, started from the same label's previous move when
     `warm`, with whole-chain sweeps when `whole_chains` (the default: move
@@ -509,7 +510,7 @@ def alpha_expansion(data, lam, labels, kind=V_TRUNC_LINEAR, trunc=2.0, max_cycle
     lib = load_library()
     L, H, W, dp, lp, dev = _ml_args(data, lam, labels)
     st = MLStats()
-    o = make_opts(max_iters, check_every, gap_tol, VARIANT_AUTO, 1e-3, validate, False, whole_chains)
+    o = make_opts(max_iters, check_every, gap_tol, variant, 1e-3, validate, False, whole_chains)
     if warm:
         o.flags |= MC_WARM_MOVES
     rc = lib.mc_alpha_expansion(context(dev), ctypes.byref(_grid((H, W))), L, dp, ctypes.cast(lp, ctypes.c_void_p),

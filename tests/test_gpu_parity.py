@@ -254,3 +254,22 @@ def test_volume3d_full_size_exact(dev):
     assert res.converged and res.energy == e_star
     lab = res.labels.cpu().numpy()
     assert oracle.cut_energy(w, a, lab) == e_star
+
+
+def test_oversize_grid_rejected(dev):
+    """n above 2^31 - 2^24 is refused before any device work (int grid-stride
+    indexing keeps 2^24 of headroom)."""
+    import ctypes
+    from paper_1503_01563_amd import mc
+    lib = mc.load_library()
+    ctx = mc.context(0)
+    g = mc._grid((46341, 46341))  # 2,147,488,281 nodes
+    st = mc.Stats()
+    o = mc.make_opts()
+    rc = lib.mc_tv_solve(ctx, ctypes.byref(g), None, None, None, None, None, None, ctypes.byref(st),
+                         ctypes.byref(o), None)
+    assert rc == -1 and b"nodes" in lib.mc_last_error()
+    g = mc._grid((32768, 65024))  # 2^31 - 2^24 nodes: passes the size check, fails on the null arrays
+    rc = lib.mc_tv_solve(ctx, ctypes.byref(g), None, None, None, None, None, None, ctypes.byref(st),
+                         ctypes.byref(o), None)
+    assert rc == -1 and b"null" in lib.mc_last_error()
