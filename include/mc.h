@@ -41,7 +41,10 @@
  *
  * Threading.  One context per host thread; a context is bound to the device
  * it was created on.  Identical inputs give identical outputs (all
- * reductions use fixed trees; no floating-point atomics).
+ * reductions use fixed trees; no floating-point atomics).  Batched solves
+ * choose their work-item count by timing unless opts->reserved[0] fixes it;
+ * the choice is cached per context, and a different count can change the
+ * last bits of the iterates (never the certified energies).
  */
 #ifndef MC_H
 #define MC_H
