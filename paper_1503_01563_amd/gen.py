@@ -178,7 +178,7 @@ def stereo_labels(shape, seed, n_labels=16, sigma=1.2, outliers=0.1, t_data=8, l
     H, W = (int(s) for s in shape)
     L = int(n_labels)
     # background: a plane tilted along W, objects at constant labels on top
-    lo, hi = sorted(rng.integers(0, L // 2, size=2))
+    lo, hi = sorted(rng.integers(0, max(1, L // 2), size=2))
     true = np.broadcast_to(np.floor(np.linspace(lo, hi + 0.999, W)), (H, W)).astype(np.int64).copy()
     grids = np.meshgrid(np.arange(H) + 0.5, np.arange(W) + 0.5, indexing="ij")
     coords = np.stack([g.ravel() for g in grids], axis=1)

@@ -173,3 +173,22 @@ def test_invalid_arguments_are_rejected(dev):
     neg[0][2, 3] = -1.0
     with pytest.raises(mc.McError):
         mc.alpha_expansion(T(data, dev), [T(x, dev) for x in neg], ok, 1, 2.0, validate=True)
+
+
+def test_degenerate_label_sets_and_shapes(dev):
+    """One label: nothing can move; a single row and a single column: the
+    moves are chain problems; both exact and locally minimal."""
+    import torch
+    from paper_1503_01563_amd import mc
+    data, lam = problem((20, 24), 7000, 1)
+    labels = Ti(np.zeros((20, 24)), dev)
+    res = mc.alpha_expansion(T(data, dev), [T(x, dev) for x in lam], labels, 0, 0.0)
+    assert res.converged and res.accepted == 0 and res.cycles == 1 and res.energy == res.energy0
+    for shape in ((1, 90), (90, 1)):
+        data, lam = problem(shape, 7001, 6)
+        labels = Ti(np.zeros(shape), dev)
+        res = mc.alpha_expansion(T(data, dev), [T(x, dev) for x in lam], labels, 1, 2.0)
+        assert res.converged
+        f = labels.cpu().numpy()
+        assert res.energy == ml.energy(data, lam, 1, 2.0, f)
+        check_local_optimum(data, lam, 1, 2.0, f)
