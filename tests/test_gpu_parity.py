@@ -143,6 +143,8 @@ def test_solve_small_grid_exact(dev, seed):
     assert res.energy == e_star
     lab = res.labels.cpu().numpy()
     assert oracle.cut_energy(w, a, lab) == e_star
+    # every minimum cut lies between the minimal and the maximal optimal set
+    assert np.all(lab >= mn) and np.all(lab <= mx)
     ro = oracle.dr_solve(w, a, max_iters=500, gap_tol=1e-3)
     print("seed %d: gpu iters %d, oracle iters %d" % (seed, res.iters, ro["iters"]))
 
@@ -273,3 +275,30 @@ def test_oversize_grid_rejected(dev):
     rc = lib.mc_tv_solve(ctx, ctypes.byref(g), None, None, None, None, None, None, ctypes.byref(st),
                          ctypes.byref(o), None)
     assert rc == -1 and b"null" in lib.mc_last_error()
+
+
+@pytest.mark.parametrize("shape", [(48, 64), (6, 20, 24)])
+def test_positive_homogeneity_is_exact(dev, shape):
+    """Scaling w and a by 2 scales every floating-point value of the solve by 2
+    exactly, so the primal doubles bit for bit and labels and iterations agree
+    (x*(t w, t a) = t x*(w, a))."""
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid(shape, 8100)
+    r1 = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=4000, check_every=2)
+    r2 = mc.tv_solve(to_dev(2 * w, dev), [to_dev(2 * x, dev) for x in a], max_iters=4000, check_every=2,
+                     tau0=2e-3, gap_tol=2e-3)  # the thresholds and the certificate scale too
+    assert r1.converged and r2.converged and r1.iters == r2.iters
+    assert np.array_equal((2 * r1.x).cpu().numpy(), r2.x.cpu().numpy())
+    assert np.array_equal(r1.labels.cpu().numpy(), r2.labels.cpu().numpy())
+    assert r2.energy == 2 * r1.energy
+
+
+def test_transposed_grid_gives_the_same_cut_energy(dev):
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid((40, 56), 8200)
+    r = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=2000, check_every=2)
+    wt = np.ascontiguousarray(w.T)
+    at = [np.ascontiguousarray(a[1].T), np.ascontiguousarray(a[0].T)]
+    rt = mc.tv_solve(to_dev(wt, dev), [to_dev(x, dev) for x in at], max_iters=2000, check_every=2)
+    assert r.converged and rt.converged
+    assert r.energy == rt.energy == oracle.mincut(w, a, "dinic")[0]
