@@ -302,3 +302,23 @@ def test_transposed_grid_gives_the_same_cut_energy(dev):
     rt = mc.tv_solve(to_dev(wt, dev), [to_dev(x, dev) for x in at], max_iters=2000, check_every=2)
     assert r.converged and rt.converged
     assert r.energy == rt.energy == oracle.mincut(w, a, "dinic")[0]
+
+
+@pytest.mark.parametrize("workload,iters", [("image2d", 2), ("image2d", 9), ("volume3d", 2)])
+def test_full_size_iterates_match_reference(dev, workload, iters):
+    """The splitting iterates at the full workload sizes, in the launch
+    configuration the benchmark times (1024^2: one work item per SIMD, latency
+    mode; the volume: the paired x/y launch), against the FP64 reference run
+    for the same number of iterations: every entry of the primal and of the
+    state within 1e-4 relative to the largest magnitude."""
+    from paper_1503_01563_amd import mc
+    if workload == "image2d":
+        w, a = gen.config_image2d(2000)
+    else:
+        w, a = gen.config_volume3d(3000)
+    res = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=iters, gap_tol=0.0,
+                      return_z=True, check_every=iters)
+    assert res.iters == iters
+    ro = oracle.dr_solve(w, a, max_iters=iters, gap_tol=0, return_z=True)
+    assert rel_linf(res.x.cpu().numpy(), ro["x"]) <= REL_TOL
+    assert rel_linf(res.z.cpu().numpy(), ro["z"]) <= REL_TOL
