@@ -75,11 +75,11 @@ extern "C" {
                                     in overlapping pieces; faster when the chain proxes have long
                                     constant segments, slower otherwise */
 #define MC_PIECE_CHAINS 16u      /* mc_tv_solve: always sweep in overlapping pieces.  With neither this
-                                    nor MC_WHOLE_CHAINS, the splitting of 4- and 6-connected grids
-                                    (variants AUTO, TWO_SET, PRODUCT) runs its first sweeps in pieces,
-                                    counts the lanes whose bracket did not close, and sweeps whole
-                                    chains for the rest of the solve when they are 1 in 10 or more
-                                    (one extra stream synchronisation); other solvers use pieces */
+                                    nor MC_WHOLE_CHAINS, solves of 4- and 6-connected grids run their
+                                    first sweeps in pieces, count the lanes whose bracket did not close,
+                                    and sweep whole chains for the rest of the solve when they are 1 in
+                                    10 or more (one extra stream synchronisation); 8-connected grids
+                                    use pieces */
 
 /* mc_opts.variant */
 #define MC_VARIANT_AUTO 0        /* two-set form for 2D, product space for 3D */

@@ -143,6 +143,40 @@ struct SweepTimer {
 
 // ---- shared by the solve loops ----------------------------------------------------
 
+// Choice of the sweep kind when neither MC_WHOLE_CHAINS nor MC_PIECE_CHAINS is
+// set: the first sweeps of the solve run as pieces and count their lanes and
+// the lanes whose bracket did not close (they restarted further back).  When
+// that is 1 in 10 or more, the chain proxes have long constant segments and
+// the rest of the solve sweeps whole chains.  One extra synchronisation.
+struct SweepProbe {
+    mc_ctx* c;
+    Geo& g;
+    hipStream_t s;
+    bool on;
+    SweepProbe(mc_ctx* c_, Geo& g_, const mc_opts& o, hipStream_t s_)
+        : c(c_), g(g_), s(s_), on(!(o.flags & (MC_WHOLE_CHAINS | MC_PIECE_CHAINS)))
+    {
+    }
+    int start()
+    {
+        if (!on) return MC_OK;
+        MC_HIP(hipMemsetAsync(c->scnt, 0, 2 * sizeof(int), s));
+        g.restarts = c->scnt;
+        return MC_OK;
+    }
+    // after each iteration: decide once the first sweeps have run
+    int after_iteration(int launches)
+    {
+        if (!on || launches == 0) return MC_OK;
+        MC_HIP(hipMemcpyAsync(c->scnt_h, c->scnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        on = false;
+        g.restarts = nullptr;
+        if (c->scnt_h[0] > 0 && 10ll * c->scnt_h[0] >= (long long)c->scnt_h[1]) g.whole = 1;
+        return MC_OK;
+    }
+};
+
 struct CheckState {
     double cert = INFINITY, energy = INFINITY, lb = -INFINITY, tvgap = NAN;
     float tau_used = 0.f;
@@ -209,9 +243,10 @@ int finish_solve(mc_ctx* c, const Geo& g, const float* state, size_t nstate, flo
 // FISTA on the dual (Sec. 4.1-4.2) over the same chain proxes; 4- and
 // 6-connected grids.  State (z0 / z_out): the dual blocks y (BCD, FISTA) or
 // the point l projected onto K (AP), r*n floats.
-int solve_variant(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const float* z0, float* x_out,
+int solve_variant(mc_ctx* c, const Geo& g0, const float* w, const float* const* a, const float* z0, float* x_out,
                   uint8_t* labels_out, float* z_out, mc_stats* stats, const mc_opts& o, hipStream_t s)
 {
+    Geo g = g0;  // the sweep kind may change after the first sweeps
     const int r = g.ndim;
     const size_t n = (size_t)g.n;
     int rc;
@@ -259,6 +294,8 @@ int solve_variant(mc_ctx* c, const Geo& g, const float* w, const float* const* a
     double t = 1.0;
     float* y = A;   // FISTA: current y, B: previous
     float* yp = B;
+    SweepProbe probe(c, g, o, s);
+    if ((rc = probe.start())) return rc;
     while (it < o.max_iters) {
         ++it;
         const bool check = (it % o.check_every == 0) || it == o.max_iters;
@@ -300,6 +337,7 @@ int solve_variant(mc_ctx* c, const Geo& g, const float* w, const float* const* a
             y = yp;
             yp = tmp;
         }
+        if ((rc = probe.after_iteration(tm.launches))) return rc;
         if (!check) continue;
         bool done = false;
         if ((rc = run_check(c, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
@@ -625,12 +663,8 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     CheckState st;
     int it = 0;
     bool converged = false;
-    // neither sweep kind forced: the first sweeps run as pieces and count restarts
-    bool probing = !(o.flags & (MC_WHOLE_CHAINS | MC_PIECE_CHAINS));
-    if (probing) {
-        MC_HIP(hipMemsetAsync(c->scnt, 0, 2 * sizeof(int), s));
-        g.restarts = c->scnt;
-    }
+    SweepProbe probe(c, g, o, s);
+    if ((rc = probe.start())) return rc;
     float* zc = c->z;   // current state
     float* zn = c->z2;  // next state
     while (it < o.max_iters) {
@@ -669,17 +703,7 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
         float* zt = zc;
         zc = zn;
         zn = zt;
-        if (probing && tm.launches > 0) {
-            // the first sweeps of the solve ran as pieces and counted their
-            // restarts: when at least 1 in 10 lanes failed its bracket the
-            // chain proxes have long constant segments, and the rest of the
-            // solve sweeps whole chains
-            MC_HIP(hipMemcpyAsync(c->scnt_h, c->scnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-            MC_HIP(hipStreamSynchronize(s));
-            probing = false;
-            g.restarts = nullptr;
-            if (c->scnt_h[0] > 0 && 10ll * c->scnt_h[0] >= (long long)c->scnt_h[1]) g.whole = 1;
-        }
+        if ((rc = probe.after_iteration(tm.launches))) return rc;
         if (!check) continue;
         bool done = false;
         if ((rc = run_check(c, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;

@@ -112,3 +112,18 @@ def test_grid8_with_whole_chains(dev):
     res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=5000, check_every=2, whole_chains=True)
     assert res.converged
     assert res.energy == G8.mincut(w, a)[0]
+
+
+@pytest.mark.parametrize("variant", ["bcd", "fista", "bcd_dr"])
+def test_automatic_choice_in_other_solvers(dev, variant):
+    from paper_1503_01563_amd import mc
+    var = {"bcd": mc.VARIANT_BCD, "fista": mc.VARIANT_FISTA, "bcd_dr": mc.VARIANT_BCD_DR}[variant]
+    data, lam, _ = gen.stereo_labels((96, 128), 6900, n_labels=8)
+    w, a = ml.expansion_problem(data, lam, 1, 2.0, np.zeros((96, 128), np.int64), 1)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=20000, check_every=2, variant=var)
+    assert res.converged and res.whole_chains == 1
+    assert res.energy == oracle.mincut(w, a)[0]
+    w, a = gen.config_image2d(2002, (256, 256))
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=20000, check_every=2, variant=var)
+    assert res.converged and res.whole_chains == 0
+    assert res.energy == oracle.mincut(w, a, "dinic")[0]
