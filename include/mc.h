@@ -160,7 +160,7 @@ int mc_ctx_destroy(mc_ctx *ctx);
  *   stats      host, required.
  * Sweeps.  Each chain prox runs as overlapping pieces, many lanes per chain,
  * or as whole chains, one lane per chain (see MC_WHOLE_CHAINS and
- * MC_PIECE_CHAINS).  Unless forced, the splitting of 4- and 6-connected grids
+ * MC_PIECE_CHAINS).  Unless forced, every solve of a 4- or 6-connected grid
  * picks whole chains after its first sweeps when those show long constant
  * segments; stats->whole_chains tells which kind ran last.
  * Returns MC_OK when cert < gap_tol (the labels are then a minimum cut
