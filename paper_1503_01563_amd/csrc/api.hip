@@ -83,7 +83,7 @@ int ensure_ws(mc_ctx* c, size_t n, int r)
     int rr = r > c->cap_r ? r : c->cap_r;
     free_ws(c);
     const size_t fb = sizeof(float);
-    const int ry = rr > 1 ? rr - 1 : 1;
+    const int ry = rr;  // prox outputs q_j of every family (product space)
     if (hipMalloc(&c->z, fb * nn * rr) != hipSuccess || hipMalloc(&c->z2, fb * nn * rr) != hipSuccess ||
         hipMalloc(&c->y, fb * nn * ry) != hipSuccess || hipMalloc(&c->p, fb * nn * rr) != hipSuccess ||
         hipMalloc(&c->xt, fb * nn) != hipSuccess) {
@@ -413,15 +413,12 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
             if (check) MC_HIP(hipMemsetAsync(c->p, 0, sizeof(float) * R * n, s));
             MC_HIP(launch_cold_product(g, R, w, zn, s));
         } else {
-            MC_HIP(tm.begin(s));
-            MC_HIP(launch_drp_sweeps(g, 2, zc, a, q, check ? c->p : nullptr, s));
-            MC_HIP(tm.end(s));
+            // gather the zig-zag chains, then sweep all four families together
             MC_HIP(launch_zz_gather(H, W, zc + 2 * n, zc + 3 * n, a[2], a[3], zzv, zza, s));
-            if (nz > 0) {
-                MC_HIP(tm.begin(s));
-                MC_HIP(launch_prox(gz, 0, zzv, zza, zzx, check ? zzp : nullptr, s));
-                MC_HIP(tm.end(s));
-            }
+            MC_HIP(tm.begin(s));
+            MC_HIP(launch_sweeps8(g, zc, a, q, check ? c->p : nullptr, gz, zzv, zza, zzx, check ? zzp : nullptr,
+                                  s));
+            MC_HIP(tm.end(s));
             MC_HIP(launch_zz_scatter(H, W, zc + 2 * n, zc + 3 * n, zzx, check ? zzp : nullptr, q + 2 * n,
                                      q + 3 * n, c->p + 2 * n, c->p + 3 * n, s));
             MC_HIP(launch_combine4(n, zc, q, w, zn, s));
@@ -691,6 +688,12 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
             MC_HIP(tm.begin(s));
             MC_HIP(launch_dr2_cols(g, c->y, zc, zn, w, a[1], check ? c->p + n : nullptr, s));
             MC_HIP(tm.end(s));
+        } else if (r == 3) {
+            // all three families in one launch, then the averaging step
+            MC_HIP(tm.begin(s));
+            MC_HIP(launch_sweeps3(g, zc, a, c->y, check ? c->p : nullptr, s));
+            MC_HIP(tm.end(s));
+            MC_HIP(launch_combine3(n, zc, c->y, w, zn, s));
         } else {
             MC_HIP(tm.begin(s));
             MC_HIP(launch_drp_sweeps(g, r - 1, zc, a, c->y, check ? c->p : nullptr, s));

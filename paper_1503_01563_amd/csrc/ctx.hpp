@@ -16,7 +16,7 @@ struct mc_ctx {
     int cap_r = 0;      // families the single-grid workspace was sized for
     float* z = nullptr;      // r*n splitting state
     float* z2 = nullptr;     // r*n second state buffer (the sweeps never update in place)
-    float* y = nullptr;      // max(1, r-1)*n: row prox q1 (two-set) or q_j of non-final families
+    float* y = nullptr;      // r*n: row prox q1 (two-set) or the prox outputs q_j (product space)
     float* p = nullptr;      // r*n edge duals (check iterations)
     float* xt = nullptr;     // n   primal estimate -w - sum_j D_j^T p_j (check iterations)
     double* partials = nullptr;  // kReduceBlocks * kCertValues

@@ -119,6 +119,12 @@ hipError_t launch_zz_scatter(int H, int W, const float* z2, const float* z3, con
     return hipGetLastError();
 }
 
+hipError_t launch_combine3(size_t n, const float* z, const float* q, const float* w, float* zn, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_combine<3>, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, z, q, w, zn);
+    return hipGetLastError();
+}
+
 hipError_t launch_combine4(size_t n, const float* z, const float* q, const float* w, float* zn, hipStream_t s)
 {
     hipLaunchKernelGGL(k_combine<4>, dim3(blocks_for(n)), dim3(kThreads), 0, s, n, z, q, w, zn);

@@ -80,6 +80,13 @@ hipError_t launch_drp_sweeps(const Geo& g, int nfam, const float* z, const float
 
 // Product space, final family (axis r-1) fused with the average over L:
 // y_j = z_j - q_j, znew_j = y_j - (2Y - Z - u)/r; p_{r-1} when non-null.
+// 8-connected grids: the product-space sweeps of rows and columns and the
+// row prox of the straightened zig-zag chains (geometry gz) in one launch
+hipError_t launch_sweeps8(const Geo& g, const float* z, const float* const* a, float* q, float* p, const Geo& gz,
+                          const float* zzv, const float* zza, float* zzx, float* zzp, hipStream_t s);
+// volumes: the product-space sweeps of all three families in one launch,
+// q_j and p_j (nullable) at offsets j*n; the averaging step is launch_combine
+hipError_t launch_sweeps3(const Geo& g, const float* z, const float* const* a, float* q, float* p, hipStream_t s);
 hipError_t launch_drp_final(const Geo& g, int r, const float* z, float* znew, const float* q,
                             const float* a_last, const float* w, float* p_last, hipStream_t s);
 
@@ -99,6 +106,8 @@ hipError_t launch_zz_scatter(int H, int W, const float* z2, const float* z3, con
                              float* q2, float* q3, float* pdd, float* pad, hipStream_t s);
 // Product-space averaging over four families: zn_j = y_j - (2Y - Z + w)/4.
 hipError_t launch_combine4(size_t n, const float* z, const float* q, const float* w, float* zn, hipStream_t s);
+// z_j' = y_j - (2Y - Z + w) / 3 for a volume's three families
+hipError_t launch_combine3(size_t n, const float* z, const float* q, const float* w, float* zn, hipStream_t s);
 // Certificate, energy and input checks with the diagonal edges.
 hipError_t launch_cert8(const Geo& g, const float* w, const float* const* a, const float* const* p, float tau0,
                         float* xc, double* partials, double* out, hipStream_t s);

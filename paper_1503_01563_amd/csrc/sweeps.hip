@@ -494,6 +494,26 @@ k_sweep_pair(Geo g, ModeSweepP m0, ModeSweepP m1, PieceCfg c0, PieceCfg c1, int 
         sweep_piece<ModeSweepP, false, kExact>(g, 1, item - n0, m1, c1, lds);
 }
 
+// Three independent families in one launch: items [0, n0) the rows and
+// [n0, n0 + n1) the columns of g (product-space sweeps), the rest family 3:
+// the straightened zig-zag chains of an 8-connected grid (rows of gz), or
+// the depth chains of a volume (axis 2 of g)
+template <class M2, bool kRows2, bool kExact>
+__global__ void __launch_bounds__(kLanes)
+k_sweep_triple(Geo g, ModeSweepP m0, ModeSweepP m1, Geo g2, int axis2, M2 m2, PieceCfg c0, PieceCfg c1,
+               PieceCfg c2, int n0, int n1)
+{
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    if (item < n0)
+        sweep_piece<ModeSweepP, true, kExact>(g, 0, item, m0, c0, lds);
+    else if (item < n0 + n1)
+        sweep_piece<ModeSweepP, false, kExact>(g, 1, item - n0, m1, c1, lds);
+    else
+        sweep_piece<M2, kRows2, kExact>(g2, axis2, item - n0 - n1, m2, c2, lds);
+}
+
+
 inline int items_of(const Geo& g, int axis, const PieceCfg& cfg)
 {
     return (geo_nchains(g, axis) + kLanes - 1) / kLanes * cfg.pieces;
@@ -502,6 +522,31 @@ inline int items_of(const Geo& g, int axis, const PieceCfg& cfg)
 inline size_t lds_bytes(const PieceCfg& cfg)
 {
     return sizeof(float) * 2 * (size_t)(cfg.reach_lo + cfg.len + cfg.reach_hi + 1) * kPad;
+}
+
+// the launch of k_sweep_triple with the latency / throughput mode decided on
+// its total number of work items
+template <class M2, bool kRows2>
+hipError_t launch_triple(const Geo& g, const ModeSweepP& m0, const ModeSweepP& m1, const Geo& g2, int axis2,
+                         const M2& m2, bool duals, hipStream_t s)
+{
+    PieceCfg c0 = piece_config(g, 0, kDefaultItems, 0), c1 = piece_config(g, 1, kDefaultItems, 0),
+             c2 = piece_config(g2, axis2, kDefaultItems, 0);
+    const int tot = items_of(g, 0, c0) + items_of(g, 1, c1) + items_of(g2, axis2, c2);
+    c0 = piece_config(g, 0, kDefaultItems, tot);
+    c1 = piece_config(g, 1, kDefaultItems, tot);
+    c2 = piece_config(g2, axis2, kDefaultItems, tot);
+    const int n0 = items_of(g, 0, c0), n1 = items_of(g, 1, c1), n2 = items_of(g2, axis2, c2);
+    size_t shm = lds_bytes(c0);
+    if (lds_bytes(c1) > shm) shm = lds_bytes(c1);
+    if (lds_bytes(c2) > shm) shm = lds_bytes(c2);
+    if (duals)
+        hipLaunchKernelGGL((k_sweep_triple<M2, kRows2, true>), dim3(n0 + n1 + n2), dim3(kLanes), shm, s, g, m0, m1,
+                           g2, axis2, m2, c0, c1, c2, n0, n1);
+    else
+        hipLaunchKernelGGL((k_sweep_triple<M2, kRows2, false>), dim3(n0 + n1 + n2), dim3(kLanes), shm, s, g, m0,
+                           m1, g2, axis2, m2, c0, c1, c2, n0, n1);
+    return hipGetLastError();
 }
 
 template <class M, bool kExact>
@@ -662,6 +707,34 @@ hipError_t launch_drp_sweeps(const Geo& g, int nfam, const float* z, const float
     else
         hipLaunchKernelGGL(k_sweep_pair<false>, dim3(n0 + n1), dim3(kLanes), shm, s, g, m0, m1, c0, c1, n0);
     return hipGetLastError();
+}
+
+hipError_t launch_sweeps8(const Geo& g, const float* z, const float* const* a, float* q, float* p, const Geo& gz,
+                          const float* zzv, const float* zza, float* zzx, float* zzp, hipStream_t s)
+{
+    if (g.whole || gz.n == 0) {
+        const hipError_t e = launch_drp_sweeps(g, 2, z, a, q, p, s);
+        if (e != hipSuccess || gz.n == 0) return e;
+        return launch_prox(gz, 0, zzv, zza, zzx, zzp, s);
+    }
+    const size_t n = (size_t)g.n;
+    ModeSweepP m0{z, a[0], q, p};
+    ModeSweepP m1{z + n, a[1], q + n, p ? p + n : nullptr};
+    ModeProx mz{zzv, zza, zzx, zzp};
+    return launch_triple<ModeProx, true>(g, m0, m1, gz, 0, mz, p != nullptr, s);
+}
+
+hipError_t launch_sweeps3(const Geo& g, const float* z, const float* const* a, float* q, float* p, hipStream_t s)
+{
+    const size_t n = (size_t)g.n;
+    ModeSweepP m2{z + 2 * n, a[2], q + 2 * n, p ? p + 2 * n : nullptr};
+    if (g.whole) {
+        const hipError_t e = launch_drp_sweeps(g, 2, z, a, q, p, s);
+        return e != hipSuccess ? e : launch_mode(g, 2, m2, p != nullptr, s);
+    }
+    ModeSweepP m0{z, a[0], q, p};
+    ModeSweepP m1{z + n, a[1], q + n, p ? p + n : nullptr};
+    return launch_triple<ModeSweepP, false>(g, m0, m1, g, 2, m2, p != nullptr, s);
 }
 
 hipError_t launch_drp_final(const Geo& g, int r, const float* z, float* znew, const float* q,
