@@ -308,7 +308,7 @@ def test_transposed_grid_gives_the_same_cut_energy(dev):
 def test_full_size_iterates_match_reference(dev, workload, iters):
     """The splitting iterates at the full workload sizes, in the launch
     configuration the benchmark times (1024^2: one work item per SIMD, latency
-    mode; the volume: the paired x/y launch), against the FP64 reference run
+    mode; the volume: the x, y and z families in one launch), against the FP64 reference run
     for the same number of iterations: every entry of the primal and of the
     state within 1e-4 relative to the largest magnitude."""
     from paper_1503_01563_amd import mc
