@@ -118,9 +118,8 @@ def cpu_baseline(w, a, gpu_energy, budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding note in the design document); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
