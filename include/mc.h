@@ -324,11 +324,12 @@ int mc_ml_energy(mc_ctx *ctx, const mc_grid *grid, int n_labels, const float *da
  * max_cycles cycles have run.  With MC_WARM_MOVES the move of a label starts
  * from z0 = x + D_rows^T clip(p1, -a_x, a_x), x and p1 the primal and row
  * duals its previous move ended with (the moves in between change the
- * problem, so this is a starting point, not a solution).  Move problems are
+ * problem, so this is a starting point, not a solution); it needs the two-set
+ * splitting (opts->variant AUTO or TWO_SET, else INVALID_ARG).  Move problems are
  * flat where the labels agree, so their chain proxes have long constant
  * segments: MC_WHOLE_CHAINS suits them (2.6x faster on a 384x288, 16-label
  * stereo-like problem).  Workspace comes from
- * the context (3 + 2 n_labels floats per pixel with MC_WARM_MOVES, 3 without);
+ * the context (4 + 2 n_labels floats per pixel with MC_WARM_MOVES, 3 without);
  * synchronises `stream`.  With MC_VALIDATE in opts->flags the weights are checked first
  * (non-finite or negative entries, non-zero last column / row). */
 int mc_alpha_expansion(mc_ctx *ctx, const mc_grid *grid, int n_labels, const float *data,

@@ -234,6 +234,9 @@ int mc_alpha_expansion(mc_ctx* c, const mc_grid* grid, int n_labels, const float
         if (c->hout[0] > 0) return set_error(MC_ERR_NONFINITE, "non-finite value in data");
     }
     const bool warm = (o.flags & MC_WARM_MOVES) != 0;
+    // the warm state is a point of the two-set splitting (n values)
+    if (warm && o.variant != MC_VARIANT_AUTO && o.variant != MC_VARIANT_TWO_SET)
+        return set_error(MC_ERR_INVALID_ARG, "MC_WARM_MOVES needs the two-set splitting (variant AUTO or TWO_SET)");
     if ((rc = ensure_ml_ws(c, n, warm ? 4 + 2 * (size_t)n_labels : 3))) return rc;
     float* w = c->mlbuf;
     float* ax = c->mlbuf + n;

@@ -169,10 +169,28 @@ def test_invalid_arguments_are_rejected(dev):
         mc.expansion_problem(T(data, dev), [T(x, dev) for x in lam], ok, 4, 1, 2.0)  # alpha out of range
     with pytest.raises(mc.McError):
         mc.alpha_expansion(T(data, dev), [T(x, dev) for x in lam], ok, 1, -1.0)  # negative truncation
+    with pytest.raises(mc.McError):  # the warm state is a point of the two-set splitting
+        mc.alpha_expansion(T(data, dev), [T(x, dev) for x in lam], ok, 1, 2.0, warm=True,
+                           variant=mc.VARIANT_PRODUCT)
     neg = [lam[0].copy(), lam[1]]
     neg[0][2, 3] = -1.0
     with pytest.raises(mc.McError):
         mc.alpha_expansion(T(data, dev), [T(x, dev) for x in neg], ok, 1, 2.0, validate=True)
+
+
+def test_moves_under_other_outer_loops(dev):
+    """The default start (warm moves) applies to the two-set splitting only;
+    with another outer loop every move starts cold and the result is the same
+    kind of local minimum."""
+    from paper_1503_01563_amd import mc
+    data, lam = problem((40, 56), 7100, 5)
+    for var in (mc.VARIANT_BCD_DR, mc.VARIANT_PRODUCT):
+        labels = Ti(np.zeros((40, 56)), dev)
+        res = mc.alpha_expansion(T(data, dev), [T(x, dev) for x in lam], labels, 1, 2.0, variant=var)
+        assert res.converged and res.uncertified == 0, var
+        f = labels.cpu().numpy()
+        assert res.energy == ml.energy(data, lam, 1, 2.0, f)
+        check_local_optimum(data, lam, 1, 2.0, f)
 
 
 def test_degenerate_label_sets_and_shapes(dev):
