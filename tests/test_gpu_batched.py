@@ -86,11 +86,15 @@ def test_batched_config_64_uneven_grids(dev):
     grids = gen.config_batch(4000)
     ws = [to_dev(w, dev) for w, _ in grids]
     As = [[to_dev(a[0], dev), to_dev(a[1], dev)] for _, a in grids]
-    res = mc.tv_solve_batched(ws, As, max_iters=3000, check_every=2)
-    ms = np.array(res.ms)
-    print("batched 64: items %d, p50 %.2f ms, p99 %.2f ms, max iters %d"
-          % (res.items, np.percentile(ms, 50), np.percentile(ms, 99), max(res.iters)))
-    assert res.converged
+    runs = {}
+    for ce in (2, 8):  # a check every 2 iterations, and the default cadence
+        res = mc.tv_solve_batched(ws, As, max_iters=3000, check_every=ce)
+        ms = np.array(res.ms)
+        print("batched 64, check every %d: items %d, p50 %.2f ms, p99 %.2f ms, max iters %d"
+              % (ce, res.items, np.percentile(ms, 50), np.percentile(ms, 99), max(res.iters)))
+        assert res.converged
+        runs[ce] = res
     for k, (w, a) in enumerate(grids):
         e_star, _, _ = oracle.mincut(w, a, "dinic")
-        assert res.energy[k] == e_star, k
+        for ce, res in runs.items():
+            assert res.energy[k] == e_star, (k, ce)
