@@ -85,9 +85,16 @@ def apply_move(f, S, alpha):
     return f
 
 
-def alpha_expansion(data, lam, kind, trunc, f0, max_cycles=50):
+def alpha_expansion(data, lam, kind, trunc, f0, max_cycles=50, skip_unchanged=False):
     """Alpha-expansion from f0 with exact moves (minimal optimal sets by
-    max-flow).  Returns (f, energies after each accepted move, cycles, moves)."""
+    max-flow).  Returns (f, energies after each accepted move, cycles, moves).
+
+    skip_unchanged: do not solve the move of a label when no move has been
+    applied since that label's previous move.  The labels are then the same
+    as at that move, which was either rejected (an exact move finds no
+    improvement again) or applied (the expansions of alpha from its result
+    are expansions from the labels before it, so none improves on it), so the
+    applied moves and the result are those of the plain loop."""
     data = np.asarray(data, np.float64)
     L = data.shape[0]
     f = np.array(f0, np.int64, copy=True)
@@ -95,10 +102,14 @@ def alpha_expansion(data, lam, kind, trunc, f0, max_cycles=50):
     trace = [e]
     moves = 0
     cycles = 0
+    applied = 0
+    seen = [-1] * L  # applied-move count when each label's move was last solved
     for _ in range(max_cycles):
         cycles += 1
         improved = False
         for alpha in range(L):
+            if skip_unchanged and seen[alpha] == applied:
+                continue
             w, a = expansion_problem(data, lam, kind, trunc, f, alpha)
             eb, S, _ = mincut(w, a)
             moves += 1
@@ -107,6 +118,8 @@ def alpha_expansion(data, lam, kind, trunc, f0, max_cycles=50):
                 e += eb
                 trace.append(e)
                 improved = True
+                applied += 1
+            seen[alpha] = applied
         if not improved:
             break
     return f, trace, cycles, moves
