@@ -293,6 +293,7 @@ def alpha_expansion_section(seed=6000, shape=(288, 384), n_labels=16, repeats=3)
         "time_ms_piece_sweeps": 1e3 * t_piece,
         "cycles": res.cycles,
         "moves": res.moves,
+        "moves_skipped_unchanged": res.skipped,
         "accepted": res.accepted,
         "dr_iters": int(res.dr_iters),
         "energy0": res.energy0,

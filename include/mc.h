@@ -295,7 +295,9 @@ typedef struct {
     int32_t moves;        /* binary problems solved */
     int32_t accepted;     /* moves applied (those that lowered E) */
     int32_t uncertified;  /* moves whose solve stopped at opts->max_iters */
-    int32_t reserved;
+    int32_t skipped;      /* moves not solved: no move applied since the same
+                             label's previous one, so its problem and result
+                             are unchanged */
     int64_t dr_iters;     /* splitting iterations over all moves */
     double energy0;       /* E(f) of the labels passed in, FP64 */
     double energy;        /* E(f) of the labels returned, FP64 */
@@ -321,7 +323,9 @@ int mc_ml_energy(mc_ctx *ctx, const mc_grid *grid, int n_labels, const float *da
  * alpha = 0..n_labels-1, each move solved exactly by mc_tv_solve with `opts`
  * (nullable: defaults; the move's labels are its certified minimum cut) and
  * applied when its energy is negative, until a cycle applies no move or
- * max_cycles cycles have run.  With MC_WARM_MOVES the move of a label starts
+ * max_cycles cycles have run.  The move of a label is skipped while no move
+ * has been applied since its previous one (same labels, same result: the
+ * applied moves are those of the plain cycles).  With MC_WARM_MOVES the move of a label starts
  * from z0 = x + D_rows^T clip(p1, -a_x, a_x), x and p1 the primal and row
  * duals its previous move ended with (the moves in between change the
  * problem, so this is a starting point, not a solution); it needs the two-set

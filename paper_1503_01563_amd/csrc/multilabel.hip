@@ -244,6 +244,12 @@ int mc_alpha_expansion(mc_ctx* c, const mc_grid* grid, int n_labels, const float
     float* z0 = c->mlbuf + 3 * n;    // warm moves: start state
     float* hist = c->mlbuf + 4 * n;  // warm moves: [label][x; p1]
     std::vector<char> have(warm ? n_labels : 0, 0);
+    // applied-move count when each label's move was last solved: while no
+    // move has been applied since, the labels are those of that move, which
+    // was rejected (an exact move finds nothing again) or applied (expansions
+    // of alpha from its result are expansions from the labels before it), so
+    // the move is skipped without changing the applied moves or the result
+    std::vector<int> seen(n_labels, -1);
     const float* a[2] = {ax, ay};
     mc_grid g2 = *grid;
     g2.conn = 4;
@@ -259,6 +265,10 @@ int mc_alpha_expansion(mc_ctx* c, const mc_grid* grid, int n_labels, const float
         ++stats->cycles;
         bool improved = false;
         for (int alpha = 0; alpha < n_labels; ++alpha) {
+            if (seen[alpha] == stats->accepted) {
+                ++stats->skipped;
+                continue;
+            }
             MC_HIP(launch_expand_build(g, data, lam, v_kind, v_trunc, labels, alpha, w, ax, ay, s));
             const float* start = nullptr;
             if (warm && have[alpha]) {
@@ -285,6 +295,7 @@ int mc_alpha_expansion(mc_ctx* c, const mc_grid* grid, int n_labels, const float
                 ++stats->accepted;
                 improved = true;
             }
+            seen[alpha] = stats->accepted;
         }
         settled = !improved;
     }

@@ -65,7 +65,7 @@ class Stats(ctypes.Structure):
 
 class MLStats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("cycles", ctypes.c_int32), ("moves", ctypes.c_int32),
-                ("accepted", ctypes.c_int32), ("uncertified", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("accepted", ctypes.c_int32), ("uncertified", ctypes.c_int32), ("skipped", ctypes.c_int32),
                 ("dr_iters", ctypes.c_int64), ("energy0", ctypes.c_double), ("energy", ctypes.c_double),
                 ("ms", ctypes.c_float), ("reserved2", ctypes.c_float)]
 
@@ -497,6 +497,7 @@ class MLResult:
     energy0: float
     energy: float
     ms: float
+    skipped: int = 0
 
     @property
     def converged(self):
@@ -531,4 +532,4 @@ def alpha_expansion(data, lam, labels, kind=V_TRUNC_LINEAR, trunc=2.0, max_cycle
                                 ctypes.byref(st), ctypes.byref(o), _stream(dev))
     _check(rc, allow_not_converged=True)
     return MLResult(st.status, st.cycles, st.moves, st.accepted, st.uncertified, st.dr_iters, st.energy0,
-                    st.energy, st.ms)
+                    st.energy, st.ms, st.skipped)

@@ -102,6 +102,8 @@ def test_alpha_expansion_reaches_a_local_minimum(dev, kind, trunc, shape, L, see
     labels = Ti(np.zeros(shape), dev)
     res = mc.alpha_expansion(T(data, dev), [T(x, dev) for x in lam], labels, kind, trunc, warm=warm)
     assert res.converged and res.uncertified == 0
+    # every cycle visits every label once: solved or skipped as unchanged
+    assert res.moves + res.skipped == res.cycles * L and res.skipped > 0
     f = labels.cpu().numpy()
     assert f.min() >= 0 and f.max() < L
     e = ml.energy(data, lam, kind, trunc, f)
