@@ -292,6 +292,14 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
         }
         items = best;
         c->tuned_items[sig] = best;
+    } else {
+        // as many iterations as the autotuner runs, so that every call checks
+        // at the same iterations (and reports the same results) whether it
+        // tuned or not
+        for (int k = 0; k < kNumCandidates && it + 1 < o.max_iters; ++k) {
+            MC_HIP(launch_batch_iteration(bl, it & 1, false, s));
+            ++it;
+        }
     }
     if ((it & 1) && it < o.max_iters) {  // an even iteration count before the graph (its parity)
         MC_HIP(launch_batch_iteration(bl, it & 1, false, s));

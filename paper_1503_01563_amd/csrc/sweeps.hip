@@ -473,6 +473,121 @@ __global__ void __launch_bounds__(kLanes) k_sweep_whole(Geo g, int axis, M mode)
     }
 }
 
+// Whole chains staged in LDS: cpi chains per work item (lanes cpi..63 idle)
+// with all m positions of their scan input and weights in LDS, so the scan
+// never waits on global memory.  A scan position is known only after the
+// previous step (a rescan jumps back), so read from global memory every loop
+// iteration waits one round trip; when only a few waves run (whole chains are
+// chosen for flat data, one lane per chain) nothing hides that latency.
+// LDS [position][chain] with pitch cpi + 1: column cpi takes the reads of idle
+// lanes, row m the writes of lanes with nothing to emit.  Loads and stores
+// walk (chain, position) flattened over the lanes, the contiguous index
+// fastest (positions for rows, chains for columns and depth).
+constexpr size_t kWholeLdsBytes = 48 * 1024;
+
+__host__ __device__ inline int whole_lds_cpi(int m)
+{
+    const int pad = (int)(kWholeLdsBytes / (2 * sizeof(float) * ((size_t)m + 1)));
+    return pad - 1 < kLanes ? pad - 1 : kLanes;
+}
+
+template <class M, bool kRows, bool kExact>
+__global__ void __launch_bounds__(kLanes) k_sweep_whole_lds(Geo g, int axis, M mode, int cpi)
+{
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    const int lane = threadIdx.x;
+    const int m = geo_extent(g, axis);
+    const int nch = geo_nchains(g, axis);
+    const int c0 = blockIdx.x * cpi;
+    const int nrows = nch - c0 < cpi ? nch - c0 : cpi;
+    const bool valid = lane < nrows;
+    const int pad = cpi + 1;
+    const int col = valid ? lane : cpi;
+    float* lv = lds;                          // [position][chain]: v, later segment value
+    float* la = lds + (size_t)(m + 1) * pad;  // [position][chain]: a, later edge dual
+    const int total = nrows * m;
+    // element e of the work item -> chain r and position q
+    auto elem = [&](int e, int& r, int& q) {
+        if (kRows) {
+            r = e / m;
+            q = e - r * m;
+        } else {
+            q = e / nrows;
+            r = e - q * nrows;
+        }
+    };
+    constexpr int B = 16;
+    for (int e0 = 0; e0 < total; e0 += kLanes * B) {
+        float vv[B], aa[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            if (e < total) {
+                int r, q;
+                elem(e, r, q);
+                const Chain ch = chain_of(g, axis, c0 + r);
+                const int i = ch.base + q * ch.stride;
+                vv[u] = mode.v_at(i);
+                aa[u] = mode.a_at(i);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            if (e < total) {
+                int r, q;
+                elem(e, r, q);
+                lv[q * pad + r] = vv[u];
+                la[q * pad + r] = aa[u];
+            }
+        }
+    }
+    wave_fence();
+
+    auto at = [&](int q) -> RingVals<2> {
+        const int sl = q * pad + col;
+        return {{lv[sl], la[sl]}};
+    };
+    auto emit = [&](int q, auto cv, auto pr, bool last, bool on) {
+        const int sl = (on ? q : m) * pad + col;
+        lv[sl] = (float)cv;
+        if constexpr (kExact) la[sl] = last ? 0.f : clip_dual(pr, la[sl]);
+    };
+    auto no_weight_before = [](int) { return 0.f; };  // never read: the scan starts at the chain start
+    PieceLane<2, kExact> pl;
+    pl.begin(valid, m, 0, m, 1, no_weight_before);
+    while (__any(pl.busy())) {
+        const RingVals<2> rf = at(pl.fill_pos(0)), rl = at(pl.l_pos(0));
+        pl.fill(rf, emit);
+        pl.step_l(rl);
+    }
+    wave_fence();
+
+    constexpr int S = 8;
+    for (int e0 = 0; e0 < total; e0 += kLanes * S) {
+        int idx[S];
+        float cv[S], pv[S];
+        typename M::Pre pre[S];
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            idx[u] = -1;
+            if (e < total) {
+                int r, q;
+                elem(e, r, q);
+                const Chain ch = chain_of(g, axis, c0 + r);
+                idx[u] = ch.base + q * ch.stride;
+                cv[u] = lv[q * pad + r];
+                pv[u] = kExact ? la[q * pad + r] : 0.f;
+                pre[u] = mode.pre(idx[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < S; ++u)
+            if (idx[u] >= 0) mode.store(idx[u], pre[u], cv[u], pv[u]);
+    }
+}
+
 template <class M, bool kRows, bool kExact>
 __global__ void __launch_bounds__(kLanes) k_sweep(Geo g, int axis, M mode, PieceCfg cfg)
 {
@@ -564,6 +679,21 @@ template <class M>
 hipError_t launch_mode(const Geo& g, int axis, const M& mode, bool duals, hipStream_t s)
 {
     if (g.whole) {
+        const int m = geo_extent(g, axis);
+        const int cpi = whole_lds_cpi(m);
+        if (cpi >= 1) {  // whole chains staged in LDS
+            const dim3 grid((geo_nchains(g, axis) + cpi - 1) / cpi), block(kLanes);
+            const size_t shm = 2 * sizeof(float) * ((size_t)m + 1) * (size_t)(cpi + 1);
+            if (axis == 0) {
+                if (duals) hipLaunchKernelGGL((k_sweep_whole_lds<M, true, true>), grid, block, shm, s, g, axis, mode, cpi);
+                else hipLaunchKernelGGL((k_sweep_whole_lds<M, true, false>), grid, block, shm, s, g, axis, mode, cpi);
+            } else {
+                if (duals) hipLaunchKernelGGL((k_sweep_whole_lds<M, false, true>), grid, block, shm, s, g, axis, mode, cpi);
+                else hipLaunchKernelGGL((k_sweep_whole_lds<M, false, false>), grid, block, shm, s, g, axis, mode, cpi);
+            }
+            return hipGetLastError();
+        }
+        // chains too long for LDS: every position from global memory
         const dim3 grid((geo_nchains(g, axis) + kLanes - 1) / kLanes), block(kLanes);
         if (duals) hipLaunchKernelGGL((k_sweep_whole<M, true>), grid, block, 0, s, g, axis, mode);
         else hipLaunchKernelGGL((k_sweep_whole<M, false>), grid, block, 0, s, g, axis, mode);
