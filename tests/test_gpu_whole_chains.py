@@ -42,6 +42,21 @@ def test_iterates_match_reference(dev, shape, variant, iters):
     assert np.abs(x - ref["x"]).max() / scale <= REL_TOL
 
 
+@pytest.mark.parametrize("shape", [(3, 4000), (4000, 2), (2, 3071), (2, 3072)])
+@pytest.mark.parametrize("iters", [2, 9])
+def test_long_chains_match_reference(dev, shape, iters):
+    """Chains too long to stage whole in LDS (more than 3071 positions) are
+    read from global memory; both kinds, and the boundary, against the
+    reference iterates."""
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid(shape, 950 + iters)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=iters, gap_tol=0.0, whole_chains=True)
+    ref = oracle.dr_solve(w, a, max_iters=iters, gap_tol=0.0)
+    x = res.x.cpu().numpy()
+    scale = max(1.0, np.abs(ref["x"]).max())
+    assert np.abs(x - ref["x"]).max() / scale <= REL_TOL
+
+
 @pytest.mark.parametrize("seed", range(1000, 1006))
 def test_exact_against_maxflow(dev, seed):
     from paper_1503_01563_amd import mc
