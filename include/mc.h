@@ -331,7 +331,7 @@ int mc_ml_energy(mc_ctx *ctx, const mc_grid *grid, int n_labels, const float *da
  * problem, so this is a starting point, not a solution); it needs the two-set
  * splitting (opts->variant AUTO or TWO_SET, else INVALID_ARG).  Move problems are
  * flat where the labels agree, so their chain proxes have long constant
- * segments: MC_WHOLE_CHAINS suits them (2.6x faster on a 384x288, 16-label
+ * segments: MC_WHOLE_CHAINS suits them (3.4x faster on a 384x288, 16-label
  * stereo-like problem).  Workspace comes from
  * the context (4 + 2 n_labels floats per pixel with MC_WARM_MOVES, 3 without);
  * synchronises `stream`.  With MC_VALIDATE in opts->flags the weights are checked first
