@@ -328,8 +328,8 @@ def tv_solve_batched(ws: Sequence[torch.Tensor], As: Sequence[Sequence[torch.Ten
     items > 0 fixes the work items per sweep launch (0: tuned on first use).
     The checks run on the device without a host round trip, so a sparse
     cadence pays: on 64 uneven grids (H, W in [128, 1024]) the per-grid time
-    to the exact cut is p50 142 / p99 248 ms with checks every 8 iterations
-    against 162 / 282 ms every 2.
+    to the exact cut was p50 142 / p99 248 ms with checks every 8 iterations
+    against 162 / 282 ms every 2 (repeat calls of one session).
     """
     lib = load_library()
     ng = len(ws)
