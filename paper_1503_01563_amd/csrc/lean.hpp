@@ -1,0 +1,237 @@
+// lean.hpp -- the chain prox scan of the sweeps that only need prox values
+// (every splitting iteration that does not evaluate the certificate), in
+// FP32, with the per-step work cut to the funnel test (Sec. 3.2 of the paper:
+// exact weighted 1D-TV prox of each chain).
+//
+// Slope form of the direct scan.  The open segment [k0, k] (value c) is
+// entered with dual A (edge k0 - 1).  The dual of edge e inside it is
+// P_e(c) = A + sum_{i=k0..e} (c - v_i), so |P_e(c)| <= a_e holds for
+//     c >= lo_e = vref + (S'_e - A - a_e) / (e - k0 + 1)   and
+//     c <= hi_e = vref + (S'_e - A + a_e) / (e - k0 + 1),
+// S'_e = sum_{i=k0..e} (v_i - vref), vref = v_k0.  The feasible values of the
+// open segment are [vmin, vmax] = [max lo_e, min hi_e]; kmin / kmax are the
+// last positions where the bounds were attained and amin / amax the weights
+// there.  A new element k with vmin > hi_k ends the segment at kmin with the
+// value vmin and a downward jump (dual -a_kmin); vmax < lo_k ends it at kmax
+// with vmax (dual +a_kmax); the scan then restarts after the knot.  The chain
+// end is an edge of weight 0 (the taut string is pinned there), where
+// lo = hi is the value of the last segment.  This is the same funnel as the
+// taut string and as Condat's direct algorithm, evaluated from the running
+// sum at every step instead of by increments, so no rounding accumulates in
+// the bounds beyond the running sum itself.
+//
+// Precision.  Every bound is formed as vref + (S' + (nA -+ a)) / len with
+// nA = -A: the two weights are combined first, so large weights that cancel
+// (a knot dual of a segment against the next edge) cancel exactly, and the
+// quotient is added to a reference value of the segment itself.  The
+// reciprocal of len is the hardware one (1 ulp).
+//
+// Knots of the scan that finishes a piece go to LDS: the segment value at the
+// knot's slot and a negative weight as its mark (weights are >= 0, staged as
+// a + 0 so that a -0 weight does not look like a mark).  After the scan a
+// backward pass over the piece gives every position the value of the next
+// mark at or after it; the segment covering the piece's last position comes
+// from registers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mc {
+
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ float lean_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+#else
+__host__ __device__ inline float lean_rcp(float x) { return 1.f / x; }
+#endif
+
+// State of one scan (FP32).  len = elements in the open segment (0: the next
+// step opens one at k).
+struct LeanScan {
+    int k;
+    bool on;
+    float nA;  // minus the dual of the edge in front of the open segment
+    float vref, s, len;
+    float vmin, vmax, amin, amax;
+    int kmin, kmax;
+};
+
+__host__ __device__ inline void lean_start(LeanScan& S, int k0, float A, bool on)
+{
+    S.k = k0;
+    S.on = on;
+    S.nA = -A;
+    S.vref = 0.f;
+    S.s = 0.f;
+    S.len = 0.f;
+    S.vmin = -__builtin_huge_valf();
+    S.vmax = __builtin_huge_valf();
+    S.amin = S.amax = 0.f;
+    S.kmin = S.kmax = k0;
+}
+
+// One step at position S.k: vk = v(k), ak = weight of edge k (0 for the
+// chain's last element m - 1).  Returns true when a segment is finished: it
+// ends at kend with value c.  After a knot the scan continues at kend + 1
+// with S.nA the negated knot dual; after the chain's last segment S.on is
+// false.
+__host__ __device__ inline bool lean_step(LeanScan& S, int m, float vk, float ak, int& kend, float& c)
+{
+    const bool opening = S.len == 0.f;
+    const float vr = opening ? vk : S.vref;
+    const float s1 = S.s + (vk - vr);
+    const float len1 = S.len + 1.f;
+    const float inv = lean_rcp(len1);
+    const float lo = __builtin_fmaf(s1 + (S.nA - ak), inv, vr);
+    const float hi = __builtin_fmaf(s1 + (S.nA + ak), inv, vr);
+    const bool down = S.vmin > hi;  // even the smallest value overflows edge k
+    const bool up = S.vmax < lo;    // even the largest underflows it
+    const bool knot = down | up;
+    const bool tl = lo >= S.vmin, tu = hi <= S.vmax;
+    const bool last = S.k == m - 1;
+
+    // the finished segment: at a knot the old bound, at the chain end the
+    // common value of both bounds
+    kend = down ? S.kmin : (up ? S.kmax : m - 1);
+    c = down ? S.vmin : (up ? S.vmax : lo);
+    const float nA_knot = down ? S.amin : -S.amax;
+
+    // After a knot at k - 1 the next segment starts at k itself: open it with
+    // this element at once (its bounds are the one-element ones, from the
+    // knot's dual).  After a knot further back the scan resumes at kend + 1
+    // (the next step opens there); at the chain's last element a knot always
+    // resumes, so that the last one-element segment is finished by a step.
+    const float nA_next = knot ? nA_knot : S.nA;
+    const bool reopen = knot & (kend + 1 == S.k) & !last;
+    const bool rescan = knot & !reopen;
+    const float lo1 = vk + (nA_next - ak), hi1 = vk + (nA_next + ak);
+    S.kmin = reopen | tl ? S.k : S.kmin;
+    S.amin = reopen | tl ? ak : S.amin;
+    S.kmax = reopen | tu ? S.k : S.kmax;
+    S.amax = reopen | tu ? ak : S.amax;
+    S.vref = reopen ? vk : vr;
+    const float inf = __builtin_huge_valf();
+    S.vmin = reopen ? lo1 : (rescan ? -inf : (tl ? lo : S.vmin));
+    S.vmax = reopen ? hi1 : (rescan ? inf : (tu ? hi : S.vmax));
+    S.s = knot ? 0.f : s1;
+    S.len = reopen ? 1.f : (rescan ? 0.f : len1);
+    S.nA = nA_next;
+    S.k = rescan ? kend + 1 : S.k + 1;
+    S.on = S.on & (knot | !last);
+    return knot | last;
+}
+
+// One lane's piece [b0, b1) of a chain of length m.  Two scans bracket the
+// unknown dual at the start p0 = b0 - W (start duals -a and +a, see
+// chain.hpp); each only advances while its last knot is not ahead of the
+// other's, and the first knot both emit (same position, same side) is a knot
+// of the true solution.  If that knot lies before b0, U stops and L goes on
+// alone, exact from there; otherwise the lane restarts with a four times
+// longer overlap (from the chain start the dual is 0 and L alone is exact).
+struct LeanLane {
+    int m, b0, b1, W;
+    bool bracket;   // L and U both running
+    bool scanning;  // the segment covering b1 - 1 is not finished yet
+    LeanScan L, U;
+    int lastL, lastU;    // position of each scan's last knot (-1: none)
+    float ancL, ancU;    // its negated dual
+    float c_last;        // value of the segment covering b1 - 1
+
+    template <class AAt>
+    __host__ __device__ inline void restart(const AAt& a_before)
+    {
+        const int p0 = b0 - W > 0 ? b0 - W : 0;
+        lastL = lastU = -1;
+        ancL = ancU = 0.f;
+        if (p0 == 0) {
+            bracket = false;
+            lean_start(L, 0, 0.f, true);
+            lean_start(U, 0, 0.f, false);
+        } else {
+            const float ab = a_before(p0 - 1);
+            bracket = true;
+            lean_start(L, p0, -ab, true);
+            lean_start(U, p0, ab, true);
+        }
+    }
+
+    template <class AAt>
+    __host__ __device__ inline void begin(bool active, int m_, int b0_, int b1_, int W0, const AAt& a_before)
+    {
+        m = m_;
+        b0 = b0_;
+        b1 = b1_;
+        W = W0;
+        scanning = active;
+        c_last = 0.f;
+        restart(a_before);
+        if (!active) L.on = U.on = false;
+    }
+
+    __host__ __device__ inline bool steps_l() const { return scanning && !(bracket && lastL > lastU); }
+    __host__ __device__ inline bool needs_u() const { return scanning && bracket && lastU <= lastL; }
+    // positions the next step_l / step_u read (`idle` when the step will not
+    // read).  Both are read before step_l, which can change whether U steps,
+    // so U's position is read whenever it brackets.
+    __host__ __device__ inline int l_pos(int idle) const { return steps_l() ? L.k : idle; }
+    __host__ __device__ inline int u_pos(int idle) const { return scanning && bracket ? U.k : idle; }
+
+    // Advance L; vk, ak at l_pos().  mark(kend, c) records a knot inside the
+    // piece (kend in [b0, b1 - 1)) once the bracket is resolved.
+    template <class Mark>
+    __host__ __device__ inline void step_l(float vk, float ak, const Mark& mark)
+    {
+        if (!steps_l()) return;
+        int kend;
+        float c;
+        const bool fin = lean_step(L, m, vk, ak, kend, c);
+        const bool br = bracket;
+        lastL = fin && br ? kend : lastL;
+        ancL = fin && br ? L.nA : ancL;
+        const bool out = fin && !br;
+        mark(kend, c, out && kend >= b0 && kend < b1 - 1);
+        const bool covers = out && kend >= b1 - 1;
+        c_last = covers ? c : c_last;
+        scanning = scanning && !covers;
+    }
+
+    // Advance L once no lane brackets any more (every lane is exact from its
+    // merge knot or from the chain start); vk, ak at L.k.
+    template <class Mark>
+    __host__ __device__ inline void step_plain(float vk, float ak, const Mark& mark)
+    {
+        int kend;
+        float c;
+        const bool fin = lean_step(L, m, vk, ak, kend, c);
+        mark(kend, c, fin & (kend >= b0) & (kend < b1 - 1));
+        const bool covers = fin & (kend >= b1 - 1);
+        c_last = covers ? c : c_last;
+        scanning = !covers;
+    }
+
+    // advance U; vk, ak at u_pos()
+    __host__ __device__ inline void step_u(float vk, float ak)
+    {
+        if (!needs_u()) return;
+        int kend;
+        float c;
+        const bool fin = lean_step(U, m, vk, ak, kend, c);
+        lastU = fin ? kend : lastU;
+        ancU = fin ? U.nA : ancU;
+    }
+
+    // after both scans stepped: merged, failed, or keep going
+    template <class AAt>
+    __host__ __device__ inline void resolve(const AAt& a_before)
+    {
+        if (!scanning || !bracket) return;
+        if (lastL == lastU && lastL >= 0 && ancL == ancU && lastL < b0 && L.on) {
+            bracket = false;  // merged at a knot before the piece: L is exact from here
+            U.on = false;
+        } else if ((lastL >= b0 - 1 && lastU >= b0 - 1) || !L.on || !U.on) {
+            W *= 4;  // no shared knot before the piece: start further back
+            restart(a_before);
+        }
+    }
+};
+
+}  // namespace mc

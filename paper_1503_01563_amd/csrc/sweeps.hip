@@ -32,6 +32,7 @@
 
 #include "chain.hpp"
 #include "launch.hpp"
+#include "lean.hpp"
 #include "piece.hpp"
 
 namespace mc {
@@ -260,7 +261,7 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
                     if (rr < nrows) {
                         const int i = (c0 + rr) * g.W + qa + q;
                         vv[u] = mode.v_at(i);
-                        aa[u] = mode.a_at(i);
+                        aa[u] = mode.a_at(i) + 0.f;
                     }
                     rr += drr;
                     q += dq;
@@ -293,7 +294,7 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
                     if (q < qb) {
                         const int i = ch.base + q * ch.stride;
                         vv[u] = mode.v_at(i);
-                        aa[u] = mode.a_at(i);
+                        aa[u] = mode.a_at(i) + 0.f;
                     }
                 }
 #pragma unroll
@@ -336,8 +337,81 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
         if constexpr (kExact) la[sl] = last ? 0.f : clip_dual(pr, la[sl]);
     };
     constexpr int kGrow = 8;
-    PieceLane<2, kExact> pl;
     const int W0 = cfg.overlap > 0 ? cfg.overlap : 1;
+    if constexpr (!kExact) {
+        // values only: the lean scan marks knots in LDS, a backward pass fills
+        LeanLane pl;
+        pl.begin(valid, m, b0, b1, W0, a_before);
+        auto mark = [&](int q, float cv, bool on) {
+            const int sl = (on ? q - base : slots) * kPad + lane;
+            lv[sl] = cv;
+            la[sl] = -1.f;
+        };
+        auto grow = [&]() {
+            if (hi < hi_cap && __any(pl.scanning && pl.L.k >= hi)) {
+                const int nh = hi + kGrow < hi_cap ? hi + kGrow : hi_cap;
+                stage(hi, nh, Small{});
+                hi = nh;
+            }
+        };
+        // Slot of position q for a scan read.  A position outside the window
+        // (rare: the deeper overlap after a failed bracket, a tail beyond the
+        // reserve) is fetched from global memory into the lane's slot of the
+        // spare row first, so that the read itself is always an LDS read.
+        const int spare = slots * kPad + lane;
+        auto slot_of = [&](int q) {
+            const bool in = (q >= lo) & (q < hi);
+            if (__any(!in)) {
+                if (!in) {
+                    const int i = ch.base + q * ch.stride;
+                    lv[spare] = mode.v_at(i);
+                    la[spare] = mode.a_at(i);
+                }
+                wave_fence();
+            }
+            return in ? (q - base) * kPad + lane : spare;
+        };
+        // while some lane brackets: both scans, U only where it brackets
+        while (__any(pl.bracket && pl.scanning)) {
+            grow();
+            const int ql = pl.l_pos(lo), qu = pl.u_pos(lo);
+            const int sl = slot_of(ql);
+            const float vl = lv[sl], al = la[sl];
+            const int su = slot_of(qu);
+            const float vu = lv[su], au = la[su];
+            pl.step_l(vl, ql + 1 < m ? al : 0.f, mark);
+            pl.step_u(vu, qu + 1 < m ? au : 0.f);
+            pl.resolve(a_before);
+        }
+        // then L alone in every lane until its piece is covered
+        while (__any(pl.scanning)) {
+            grow();
+            const int ql = pl.scanning ? pl.L.k : lo;
+            const int sl = slot_of(ql);
+            const float vl = lv[sl], al = la[sl];
+            if (pl.scanning) pl.step_plain(vl, ql + 1 < m ? al : 0.f, mark);
+        }
+        wave_fence();
+        if (g.restarts) {
+            const int nr = __popcll(__ballot(valid && pl.W != W0));
+            const int nv = __popcll(__ballot(valid));
+            if (lane == 0) {
+                atomicAdd(g.restarts, nr);
+                atomicAdd(g.restarts + 1, nv);
+            }
+        }
+        // every position takes the value of the first knot at or after it;
+        // the segment covering b1 - 1 is in registers
+        float cur = pl.c_last;
+        for (int q = b1 - 1; q >= b0; --q) {
+            const int sl = (q - base) * kPad + lane;
+            const float aq = la[sl], vq = lv[sl];
+            cur = aq < 0.f ? vq : cur;
+            lv[sl] = cur;
+        }
+        wave_fence();
+    } else {
+    PieceLane<2, kExact> pl;
     pl.begin(valid, m, b0, b1, W0, a_before);
     while (__any(pl.busy())) {
         // some lane's scan is about to read past the window: stage the next block
@@ -373,6 +447,7 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
             atomicAdd(g.restarts, nr);
             atomicAdd(g.restarts + 1, nv);
         }
+    }
     }
 
     // store
