@@ -173,6 +173,32 @@ int mc_tv_solve(mc_ctx *ctx, const mc_grid *grid, const float *w,
                 const mc_opts *opts, void *stream);
 
 /*
+ * mc_tv_solve_noalloc -- mc_tv_solve without any device allocation, for
+ * callers that cannot allocate: code that runs while a HIP graph is being
+ * captured, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as mc_tv_solve, restricted to 4- and
+ * 6-connected grids and the splitting variants MC_VARIANT_AUTO, _TWO_SET and
+ * _PRODUCT (others, an 8-connected grid, and MC_PROFILE give
+ * MC_ERR_INVALID_ARG).  Its workspace is one static device array per GPU,
+ * reserved when the library's code object is loaded on that GPU and held
+ * until the process ends: 32 MiB of solver state plus the reduction
+ * partials.  The state needs 24 bytes per node in the two-set form and
+ * 4 (4 r + 1) bytes per node in the product space (r families), so grids
+ * up to about 1.39 M nodes in 2D (two-set) and 645 k nodes in 3D fit;
+ * larger ones give MC_ERR_INVALID_ARG with the sizes in mc_last_error().
+ * Every call on one GPU uses that GPU's array, from any context: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  The array keeps the last call's contents; each
+ * call sets what it reads before reading it.  The context must have been
+ * created on the GPU (mc_ctx_create takes the array's device address).
+ * Like mc_tv_solve it synchronises the stream at every certificate.
+ */
+int mc_tv_solve_noalloc(mc_ctx *ctx, const mc_grid *grid, const float *w,
+                        const float *const *a, const float *z0, float *x_out,
+                        uint8_t *labels_out, float *z_out, mc_stats *stats,
+                        const mc_opts *opts, void *stream);
+
+/*
  * mc_tv_prox_chains -- exact weighted 1D-TV prox of every line along `axis`
  * (Sec. 3.2): for each chain, x = argmin 1/2|x - v|^2 + sum_e a_e |x_{e+1} - x_e|.
  *   v, a_axis  [n] input and weights along the axis.

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -96,6 +97,21 @@ int ensure_ws(mc_ctx* c, size_t n, int r)
     return MC_OK;
 }
 
+// Device buffers of one single-grid solve: the context's workspace, or the
+// static scratch array of mc_tv_solve_noalloc.
+struct SolveWs {
+    float* z;          // splitting state (n two-set, r*n product space)
+    float* z2;         // next state
+    float* y;          // prox outputs: q1 (two-set) or q_j (r*n)
+    float* p;          // r*n edge duals of check iterations
+    float* xt;         // n primal estimate
+    double* partials;  // kReduceBlocks * kCertValues
+    double* dout;      // kCertValues
+    int* scnt;         // 2 counters of the sweep-kind probe
+};
+
+SolveWs ctx_ws(mc_ctx* c) { return {c->z, c->z2, c->y, c->p, c->xt, c->partials, c->dout, c->scnt}; }
+
 // Counts the chain-sweep launches; with MC_PROFILE also brackets each with a
 // pair of events from a pool, drained at every synchronisation point of the
 // solve.  (An event record costs a few microseconds of stream time.)
@@ -150,25 +166,26 @@ struct SweepTimer {
 // the rest of the solve sweeps whole chains.  One extra synchronisation.
 struct SweepProbe {
     mc_ctx* c;
+    int* cnt;
     Geo& g;
     hipStream_t s;
     bool on;
-    SweepProbe(mc_ctx* c_, Geo& g_, const mc_opts& o, hipStream_t s_)
-        : c(c_), g(g_), s(s_), on(!(o.flags & (MC_WHOLE_CHAINS | MC_PIECE_CHAINS)))
+    SweepProbe(mc_ctx* c_, const SolveWs& ws, Geo& g_, const mc_opts& o, hipStream_t s_)
+        : c(c_), cnt(ws.scnt), g(g_), s(s_), on(!(o.flags & (MC_WHOLE_CHAINS | MC_PIECE_CHAINS)))
     {
     }
     int start()
     {
         if (!on) return MC_OK;
-        MC_HIP(hipMemsetAsync(c->scnt, 0, 2 * sizeof(int), s));
-        g.restarts = c->scnt;
+        MC_HIP(hipMemsetAsync(cnt, 0, 2 * sizeof(int), s));
+        g.restarts = cnt;
         return MC_OK;
     }
     // after each iteration: decide once the first sweeps have run
     int after_iteration(int launches)
     {
         if (!on || launches == 0) return MC_OK;
-        MC_HIP(hipMemcpyAsync(c->scnt_h, c->scnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipMemcpyAsync(c->scnt_h, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
         MC_HIP(hipStreamSynchronize(s));
         on = false;
         g.restarts = nullptr;
@@ -185,13 +202,14 @@ struct CheckState {
 
 // Certificate from the edge duals pj (Sec. 2.2): energies of the threshold
 // ladder, LB, TV gap; `done` when cert < gap_tol.  Synchronises the stream.
-int run_check(mc_ctx* c, const Geo& g, bool conn8, const float* w, const float* const* a, const float* const* pj,
-              const mc_opts& o, const float* taus, SweepTimer& tm, hipStream_t s, CheckState& st, bool& done)
+int run_check(mc_ctx* c, const SolveWs& ws, const Geo& g, bool conn8, const float* w, const float* const* a,
+              const float* const* pj, const mc_opts& o, const float* taus, SweepTimer& tm, hipStream_t s,
+              CheckState& st, bool& done)
 {
     ++st.checks;
-    if (conn8) MC_HIP(launch_cert8(g, w, a, pj, o.tau0, c->xt, c->partials, c->dout, s));
-    else MC_HIP(launch_cert(g, w, a, pj, o.tau0, c->xt, c->partials, c->dout, s));
-    MC_HIP(hipMemcpyAsync(c->hout, c->dout, kCertValues * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (conn8) MC_HIP(launch_cert8(g, w, a, pj, o.tau0, ws.xt, ws.partials, ws.dout, s));
+    else MC_HIP(launch_cert(g, w, a, pj, o.tau0, ws.xt, ws.partials, ws.dout, s));
+    MC_HIP(hipMemcpyAsync(c->hout, ws.dout, kCertValues * sizeof(double), hipMemcpyDeviceToHost, s));
     MC_HIP(hipStreamSynchronize(s));
     MC_HIP(tm.drain());
     st.energy = INFINITY;
@@ -210,14 +228,14 @@ int run_check(mc_ctx* c, const Geo& g, bool conn8, const float* w, const float* 
 }
 
 // Labels of the last certificate's primal, optional outputs, stats.
-int finish_solve(mc_ctx* c, const Geo& g, const float* state, size_t nstate, float* x_out, uint8_t* labels_out,
-                 float* z_out, mc_stats* stats, int it, bool converged, const CheckState& st, SweepTimer& tm,
-                 hipStream_t s)
+int finish_solve(mc_ctx* c, const SolveWs& ws, const Geo& g, const float* state, size_t nstate, float* x_out,
+                 uint8_t* labels_out, float* z_out, mc_stats* stats, int it, bool converged, const CheckState& st,
+                 SweepTimer& tm, hipStream_t s)
 {
     const size_t n = (size_t)g.n;
     MC_HIP(hipEventRecord(c->ev1, s));
-    MC_HIP(launch_labels(g, c->xt, st.tau_used, labels_out, s));
-    if (x_out) MC_HIP(hipMemcpyAsync(x_out, c->xt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
+    MC_HIP(launch_labels(g, ws.xt, st.tau_used, labels_out, s));
+    if (x_out) MC_HIP(hipMemcpyAsync(x_out, ws.xt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
     if (z_out) MC_HIP(hipMemcpyAsync(z_out, state, sizeof(float) * nstate, hipMemcpyDeviceToDevice, s));
     MC_HIP(hipStreamSynchronize(s));
     float ms = 0.f;
@@ -294,7 +312,8 @@ int solve_variant(mc_ctx* c, const Geo& g0, const float* w, const float* const* 
     double t = 1.0;
     float* y = A;   // FISTA: current y, B: previous
     float* yp = B;
-    SweepProbe probe(c, g, o, s);
+    const SolveWs ws = ctx_ws(c);
+    SweepProbe probe(c, ws, g, o, s);
     if ((rc = probe.start())) return rc;
     while (it < o.max_iters) {
         ++it;
@@ -340,14 +359,14 @@ int solve_variant(mc_ctx* c, const Geo& g0, const float* w, const float* const* 
         if ((rc = probe.after_iteration(tm.launches))) return rc;
         if (!check) continue;
         bool done = false;
-        if ((rc = run_check(c, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
+        if ((rc = run_check(c, ws, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
         if (done) {
             converged = true;
             break;
         }
     }
     const float* state = o.variant == MC_VARIANT_FISTA ? y : A;
-    return finish_solve(c, g, state, (size_t)r * n, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
+    return finish_solve(c, ws, g, state, (size_t)r * n, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
 }
 
 // 8-connected 2D grids: product-space splitting over rows, columns and the
@@ -428,13 +447,153 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
         zn = zt;
         if (!check) continue;
         bool done = false;
-        if ((rc = run_check(c, g, true, w, a, pj, o, taus, tm, s, st, done))) return rc;
+        if ((rc = run_check(c, ctx_ws(c), g, true, w, a, pj, o, taus, tm, s, st, done))) return rc;
         if (done) {
             converged = true;
             break;
         }
     }
-    return finish_solve(c, g, zc, R * n, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
+    return finish_solve(c, ctx_ws(c), g, zc, R * n, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
+}
+
+// opts (nullable: defaults) with the checks every single-grid solve shares
+int read_opts(const mc_opts* in, mc_opts& o)
+{
+    if (in) o = *in; else mc_opts_default(&o);
+    if (o.max_iters < 1 || o.check_every < 1) return fail(MC_ERR_INVALID_ARG, "max_iters and check_every must be >= 1");
+    if (!(o.tau0 >= 0.f)) return fail(MC_ERR_INVALID_ARG, "tau0 must be >= 0");
+    if ((o.flags & MC_WHOLE_CHAINS) && (o.flags & MC_PIECE_CHAINS))
+        return fail(MC_ERR_INVALID_ARG, "MC_WHOLE_CHAINS and MC_PIECE_CHAINS exclude each other");
+    return MC_OK;
+}
+
+// ---- scratch of mc_tv_solve_noalloc -----------------------------------------------
+//
+// One static device array per GPU, reserved when the code object loads and held
+// until the process ends: the reduction partials, the certificate values and the
+// probe counters, then up to kNoAllocFloats floats of solver state (five arrays,
+// each starting on a 256-byte boundary).  In host code `scratch` only names the
+// symbol; its device address comes from hipGetSymbolAddress, taken once per
+// device by mc_ctx_create with that device current, and only that address is
+// passed to kernels and copies.
+constexpr size_t kNoAllocFloats = size_t(1) << 23;  // 32 MiB of state
+constexpr size_t kScratchAlign = 256;
+constexpr size_t scratch_round(size_t bytes) { return (bytes + kScratchAlign - 1) / kScratchAlign * kScratchAlign; }
+constexpr size_t kScratchPartials = scratch_round(sizeof(double) * kReduceBlocks * kCertValues);
+constexpr size_t kScratchDout = scratch_round(sizeof(double) * kCertValues);
+constexpr size_t kScratchCnt = scratch_round(2 * sizeof(int));
+constexpr size_t kScratchHeader = kScratchPartials + kScratchDout + kScratchCnt;
+constexpr size_t kScratchState = sizeof(float) * kNoAllocFloats + 5 * kScratchAlign;
+constexpr int kScratchDevices = 64;
+
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kScratchDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchHeader + kScratchState];
+
+namespace {
+
+// with `device` current: its address of the scratch array (once per device)
+int scratch_setup(int device)
+{
+    if (device >= kScratchDevices) return MC_OK;  // mc_tv_solve_noalloc refuses such devices
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return MC_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = static_cast<unsigned char*>(ptr);
+    return MC_OK;
+}
+
+// The splitting method on a 4- or 6-connected grid (two-set form or product
+// space) with the device buffers of ws; arguments already checked.
+int solve_split(mc_ctx* c, const SolveWs& ws, Geo g, bool two_set, const float* w, const float* const* a,
+                const float* z0, float* x_out, uint8_t* labels_out, float* z_out, mc_stats* stats, const mc_opts& o,
+                hipStream_t s)
+{
+    int rc;
+    const int r = g.ndim;
+    const size_t n = (size_t)g.n;
+    const size_t nz = two_set ? n : (size_t)r * n;
+
+    if (o.flags & MC_VALIDATE) {
+        MC_HIP(launch_validate(g, w, a, ws.partials, ws.dout, s));
+        MC_HIP(hipMemcpyAsync(c->hout, ws.dout, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        if (c->hout[1] > 0) return fail(MC_ERR_NONFINITE, "non-finite value in w or a");
+        if (c->hout[0] > 0) return fail(MC_ERR_NEGATIVE_WEIGHT, "negative weight or non-zero weight on a last slice");
+    }
+
+    if (z0) MC_HIP(hipMemcpyAsync(ws.z, z0, sizeof(float) * nz, hipMemcpyDeviceToDevice, s));
+    else MC_HIP(hipMemsetAsync(ws.z, 0, sizeof(float) * nz, s));
+    MC_HIP(hipEventRecord(c->ev0, s));
+
+    const float* pj[3] = {ws.p, ws.p + n, ws.p + 2 * n};
+    SweepTimer tm{c, (o.flags & MC_PROFILE) != 0};
+    float taus[kNumTau];
+    tau_ladder(o.tau0, taus);
+    CheckState st;
+    int it = 0;
+    bool converged = false;
+    SweepProbe probe(c, ws, g, o, s);
+    if ((rc = probe.start())) return rc;
+    float* zc = ws.z;   // current state
+    float* zn = ws.z2;  // next state
+    while (it < o.max_iters) {
+        ++it;
+        const bool check = (it % o.check_every == 0) || it == o.max_iters;
+        // A cold start begins at z = 0, whose chain proxes are 0 with zero
+        // duals (the prox of a constant chain is the chain itself).  Sweeping
+        // that is slow -- every chain is one segment, so no bracket closes
+        // before the chain start -- and unnecessary: set the results instead.
+        const bool cold_first = it == 1 && !z0;
+        if (two_set && cold_first) {
+            MC_HIP(hipMemsetAsync(ws.y, 0, sizeof(float) * n, s));
+            if (check) MC_HIP(hipMemsetAsync(ws.p, 0, sizeof(float) * n, s));
+            MC_HIP(tm.begin(s));
+            MC_HIP(launch_dr2_cols(g, ws.y, zc, zn, w, a[1], check ? ws.p + n : nullptr, s));
+            MC_HIP(tm.end(s));
+        } else if (cold_first) {
+            if (check) MC_HIP(hipMemsetAsync(ws.p, 0, sizeof(float) * (size_t)r * n, s));
+            MC_HIP(launch_cold_product(g, r, w, zn, s));
+        } else if (two_set) {
+            MC_HIP(tm.begin(s));
+            MC_HIP(launch_dr2_rows(g, zc, a[0], ws.y, check ? ws.p : nullptr, s));
+            MC_HIP(tm.end(s));
+            MC_HIP(tm.begin(s));
+            MC_HIP(launch_dr2_cols(g, ws.y, zc, zn, w, a[1], check ? ws.p + n : nullptr, s));
+            MC_HIP(tm.end(s));
+        } else if (r == 3) {
+            // all three families in one launch, then the averaging step
+            MC_HIP(tm.begin(s));
+            MC_HIP(launch_sweeps3(g, zc, a, ws.y, check ? ws.p : nullptr, s));
+            MC_HIP(tm.end(s));
+            MC_HIP(launch_combine3(n, zc, ws.y, w, zn, s));
+        } else {
+            MC_HIP(tm.begin(s));
+            MC_HIP(launch_drp_sweeps(g, r - 1, zc, a, ws.y, check ? ws.p : nullptr, s));
+            MC_HIP(tm.end(s));
+            MC_HIP(tm.begin(s));
+            MC_HIP(launch_drp_final(g, r, zc, zn, ws.y, a[r - 1], w,
+                                    check ? ws.p + (size_t)(r - 1) * n : nullptr, s));
+            MC_HIP(tm.end(s));
+        }
+        float* zt = zc;
+        zc = zn;
+        zn = zt;
+        if ((rc = probe.after_iteration(tm.launches))) return rc;
+        if (!check) continue;
+        bool done = false;
+        if ((rc = run_check(c, ws, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
+        if (done) {
+            converged = true;
+            break;
+        }
+    }
+    return finish_solve(c, ws, g, zc, nz, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
 }
 
 }  // namespace
@@ -491,6 +650,11 @@ int mc_ctx_create(mc_ctx** out, int device)
         (void)hipGetLastError();
         mc_ctx_destroy(c);
         return fail(MC_ERR_NOMEM, "context allocation failed");
+    }
+    int rc = scratch_setup(device);
+    if (rc) {
+        mc_ctx_destroy(c);
+        return rc;
     }
     *out = c;
     return MC_OK;
@@ -570,11 +734,7 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     for (int j = 0; j < g.ndim; ++j)
         if (!a[j]) return fail(MC_ERR_INVALID_ARG, "null weight array");
     mc_opts o;
-    if (opts_in) o = *opts_in; else mc_opts_default(&o);
-    if (o.max_iters < 1 || o.check_every < 1) return fail(MC_ERR_INVALID_ARG, "max_iters and check_every must be >= 1");
-    if (!(o.tau0 >= 0.f)) return fail(MC_ERR_INVALID_ARG, "tau0 must be >= 0");
-    if ((o.flags & MC_WHOLE_CHAINS) && (o.flags & MC_PIECE_CHAINS))
-        return fail(MC_ERR_INVALID_ARG, "MC_WHOLE_CHAINS and MC_PIECE_CHAINS exclude each other");
+    if ((rc = read_opts(opts_in, o))) return rc;
     g.whole = (o.flags & MC_WHOLE_CHAINS) ? 1 : 0;
     if (grid->conn == 8) {
         if (g.ndim != 2) return fail(MC_ERR_INVALID_ARG, "8-connected grids are 2D");
@@ -637,85 +797,60 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     if (two_set && g.ndim != 2) return fail(MC_ERR_INVALID_ARG, "two-set form needs a 2D grid");
     const int r = g.ndim;
     const size_t n = (size_t)g.n;
-    const size_t nz = two_set ? n : (size_t)r * n;
     if ((rc = ensure_ws(c, n, r))) return rc;
-    hipStream_t s = (hipStream_t)stream;
+    return solve_split(c, ctx_ws(c), g, two_set, w, a, z0, x_out, labels_out, z_out, stats, o,
+                       (hipStream_t)stream);
+}
 
-    if (o.flags & MC_VALIDATE) {
-        MC_HIP(launch_validate(g, w, a, c->partials, c->dout, s));
-        MC_HIP(hipMemcpyAsync(c->hout, c->dout, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        MC_HIP(hipStreamSynchronize(s));
-        if (c->hout[1] > 0) return fail(MC_ERR_NONFINITE, "non-finite value in w or a");
-        if (c->hout[0] > 0) return fail(MC_ERR_NEGATIVE_WEIGHT, "negative weight or non-zero weight on a last slice");
+int mc_tv_solve_noalloc(mc_ctx* c, const mc_grid* grid, const float* w, const float* const* a, const float* z0,
+                        float* x_out, uint8_t* labels_out, float* z_out, mc_stats* stats, const mc_opts* opts_in,
+                        void* stream)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    Geo g;
+    if ((rc = make_geo(grid, &g))) return rc;
+    if (!w || !a || !labels_out || !stats) return fail(MC_ERR_INVALID_ARG, "null argument");
+    for (int j = 0; j < g.ndim; ++j)
+        if (!a[j]) return fail(MC_ERR_INVALID_ARG, "null weight array");
+    mc_opts o;
+    if ((rc = read_opts(opts_in, o))) return rc;
+    if (grid->conn == 8) return fail(MC_ERR_INVALID_ARG, "mc_tv_solve_noalloc: 4- and 6-connected grids only");
+    if (o.flags & MC_PROFILE) return fail(MC_ERR_INVALID_ARG, "mc_tv_solve_noalloc: MC_PROFILE needs timing events");
+    bool two_set;
+    if (o.variant == MC_VARIANT_AUTO) two_set = g.ndim == 2;
+    else if (o.variant == MC_VARIANT_TWO_SET) two_set = true;
+    else if (o.variant == MC_VARIANT_PRODUCT) two_set = false;
+    else return fail(MC_ERR_INVALID_ARG, "mc_tv_solve_noalloc: variant must be AUTO, TWO_SET or PRODUCT");
+    if (two_set && g.ndim != 2) return fail(MC_ERR_INVALID_ARG, "two-set form needs a 2D grid");
+    g.whole = (o.flags & MC_WHOLE_CHAINS) ? 1 : 0;
+    const size_t n = (size_t)g.n, r = (size_t)g.ndim;
+    const size_t nz = two_set ? n : r * n;
+    const size_t counts[5] = {nz, nz, two_set ? n : r * n, two_set ? 2 * n : r * n, n};  // z, z2, y, p, xt
+    size_t need = 0;
+    for (size_t k : counts) need += scratch_round(sizeof(float) * k);
+    if (need > kScratchState)
+        return fail(MC_ERR_INVALID_ARG, "mc_tv_solve_noalloc: the grid needs " + std::to_string(need) +
+                                            " bytes of state, the static scratch holds " +
+                                            std::to_string(kScratchState));
+    unsigned char* base = c->device < kScratchDevices ? g_scratch_ptr[c->device] : nullptr;
+    if (!base) return fail(MC_ERR_DEVICE, "mc_tv_solve_noalloc: no scratch address for this device");
+    SolveWs ws;
+    ws.partials = reinterpret_cast<double*>(base);
+    ws.dout = reinterpret_cast<double*>(base + kScratchPartials);
+    ws.scnt = reinterpret_cast<int*>(base + kScratchPartials + kScratchDout);
+    unsigned char* f = base + kScratchHeader;
+    float* arr[5];
+    for (int k = 0; k < 5; ++k) {
+        arr[k] = reinterpret_cast<float*>(f);
+        f += scratch_round(sizeof(float) * counts[k]);
     }
-
-    if (z0) MC_HIP(hipMemcpyAsync(c->z, z0, sizeof(float) * nz, hipMemcpyDeviceToDevice, s));
-    else MC_HIP(hipMemsetAsync(c->z, 0, sizeof(float) * nz, s));
-    MC_HIP(hipEventRecord(c->ev0, s));
-
-    const float* pj[3] = {c->p, c->p + n, c->p + 2 * n};
-    SweepTimer tm{c, (o.flags & MC_PROFILE) != 0};
-    float taus[kNumTau];
-    tau_ladder(o.tau0, taus);
-    CheckState st;
-    int it = 0;
-    bool converged = false;
-    SweepProbe probe(c, g, o, s);
-    if ((rc = probe.start())) return rc;
-    float* zc = c->z;   // current state
-    float* zn = c->z2;  // next state
-    while (it < o.max_iters) {
-        ++it;
-        const bool check = (it % o.check_every == 0) || it == o.max_iters;
-        // A cold start begins at z = 0, whose chain proxes are 0 with zero
-        // duals (the prox of a constant chain is the chain itself).  Sweeping
-        // that is slow -- every chain is one segment, so no bracket closes
-        // before the chain start -- and unnecessary: set the results instead.
-        const bool cold_first = it == 1 && !z0;
-        if (two_set && cold_first) {
-            MC_HIP(hipMemsetAsync(c->y, 0, sizeof(float) * n, s));
-            if (check) MC_HIP(hipMemsetAsync(c->p, 0, sizeof(float) * n, s));
-            MC_HIP(tm.begin(s));
-            MC_HIP(launch_dr2_cols(g, c->y, zc, zn, w, a[1], check ? c->p + n : nullptr, s));
-            MC_HIP(tm.end(s));
-        } else if (cold_first) {
-            if (check) MC_HIP(hipMemsetAsync(c->p, 0, sizeof(float) * (size_t)r * n, s));
-            MC_HIP(launch_cold_product(g, r, w, zn, s));
-        } else if (two_set) {
-            MC_HIP(tm.begin(s));
-            MC_HIP(launch_dr2_rows(g, zc, a[0], c->y, check ? c->p : nullptr, s));
-            MC_HIP(tm.end(s));
-            MC_HIP(tm.begin(s));
-            MC_HIP(launch_dr2_cols(g, c->y, zc, zn, w, a[1], check ? c->p + n : nullptr, s));
-            MC_HIP(tm.end(s));
-        } else if (r == 3) {
-            // all three families in one launch, then the averaging step
-            MC_HIP(tm.begin(s));
-            MC_HIP(launch_sweeps3(g, zc, a, c->y, check ? c->p : nullptr, s));
-            MC_HIP(tm.end(s));
-            MC_HIP(launch_combine3(n, zc, c->y, w, zn, s));
-        } else {
-            MC_HIP(tm.begin(s));
-            MC_HIP(launch_drp_sweeps(g, r - 1, zc, a, c->y, check ? c->p : nullptr, s));
-            MC_HIP(tm.end(s));
-            MC_HIP(tm.begin(s));
-            MC_HIP(launch_drp_final(g, r, zc, zn, c->y, a[r - 1], w,
-                                    check ? c->p + (size_t)(r - 1) * n : nullptr, s));
-            MC_HIP(tm.end(s));
-        }
-        float* zt = zc;
-        zc = zn;
-        zn = zt;
-        if ((rc = probe.after_iteration(tm.launches))) return rc;
-        if (!check) continue;
-        bool done = false;
-        if ((rc = run_check(c, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
-        if (done) {
-            converged = true;
-            break;
-        }
-    }
-    return finish_solve(c, g, zc, nz, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
+    ws.z = arr[0];
+    ws.z2 = arr[1];
+    ws.y = arr[2];
+    ws.p = arr[3];
+    ws.xt = arr[4];
+    return solve_split(c, ws, g, two_set, w, a, z0, x_out, labels_out, z_out, stats, o, (hipStream_t)stream);
 }
 
 }  // extern "C"

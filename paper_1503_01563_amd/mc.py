@@ -93,6 +93,8 @@ def load_library():
         lib.mc_tv_solve.argtypes = [P, ctypes.POINTER(Grid), P, P, P, P, P, P,
                                     ctypes.POINTER(Stats), ctypes.POINTER(Opts), P]
         lib.mc_tv_solve.restype = ctypes.c_int
+        lib.mc_tv_solve_noalloc.argtypes = lib.mc_tv_solve.argtypes
+        lib.mc_tv_solve_noalloc.restype = ctypes.c_int
         lib.mc_tv_prox_chains.argtypes = [P, ctypes.POINTER(Grid), ctypes.c_int, P, P, P, P, P]
         lib.mc_tv_prox_chains.restype = ctypes.c_int
         lib.mc_cut_energy.argtypes = [P, ctypes.POINTER(Grid), P, P, P, ctypes.POINTER(ctypes.c_double), P]
@@ -232,6 +234,23 @@ def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tens
              validate=False, return_x=True, return_z=False, labels_out=None,
              profile=False, whole_chains=None) -> SolveResult:
     """Minimum cut of one grid by mc_tv_solve."""
+    return _solve("mc_tv_solve", w, a, z0, max_iters, check_every, gap_tol, variant, tau0, validate,
+                  return_x, return_z, labels_out, profile, whole_chains)
+
+
+def tv_solve_noalloc(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tensor] = None,
+                     max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
+                     validate=False, return_x=True, return_z=False, labels_out=None,
+                     whole_chains=None) -> SolveResult:
+    """Minimum cut of one grid by mc_tv_solve_noalloc (the library's static
+    device scratch instead of context workspace; outputs are still allocated
+    here unless passed in)."""
+    return _solve("mc_tv_solve_noalloc", w, a, z0, max_iters, check_every, gap_tol, variant, tau0, validate,
+                  return_x, return_z, labels_out, False, whole_chains)
+
+
+def _solve(entry, w, a, z0, max_iters, check_every, gap_tol, variant, tau0, validate, return_x, return_z,
+           labels_out, profile, whole_chains) -> SolveResult:
     lib = load_library()
     shape = tuple(w.shape)
     nd = len(shape)
@@ -253,7 +272,7 @@ def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tens
     z = torch.empty(nz, dtype=torch.float32, device=w.device) if return_z else None
     st = Stats()
     o = make_opts(max_iters, check_every, gap_tol, variant, tau0, validate, profile, whole_chains)
-    rc = lib.mc_tv_solve(context(dev), ctypes.byref(_grid(shape, conn)), wp,
+    rc = getattr(lib, entry)(context(dev), ctypes.byref(_grid(shape, conn)), wp,
                          ctypes.cast(ap, ctypes.c_void_p), z0p,
                          ctypes.c_void_p(x.data_ptr()) if x is not None else None,
                          ctypes.c_void_p(labels.data_ptr()),
