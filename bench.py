@@ -1,21 +1,26 @@
-"""Benchmark: minimum cut of a segmentation-shaped 1024x1024 grid on one GPU.
+"""Benchmark: minimum cut of a 256x256x128 6-connected volume on one GPU.
 
-One step = one cold-start solve of the whole hot path through the C ABI:
-chain-prox sweeps (rows, columns), the two-set Douglas-Rachford update, the
-FP64 certificate checks and the cut readout, run until the certificate is
-below 1e-3 (exact for the 2^-8-dyadic data).  Inputs are generated once and
-resident in HBM before the timed region.
+One step = one cold-start solve of the whole hot path through the C ABI on the
+largest single-GPU workload (a segmentation-shaped volume, 8.4 M voxels):
+chain-prox sweeps of the three families (one launch), the product-space
+Douglas-Rachford averaging step, the FP64 certificate checks and the cut
+readout, run until the certificate is below 1e-3 (exact for the 2^-8-dyadic
+data).  Inputs are generated once and resident in HBM before the timed region.
 
 Prints one JSON line.  `value` is voxel-sweeps per second over the timed
-steps (voxels x chain families x iterations / wall time).  `roofline` rates the
-chain-sweep kernels (the dominant kernels) by their event-timed launches
-against HBM bandwidth, with 16 algorithmic bytes per voxel-sweep.
-`warm_start` compares the time to the exact cut from a cold start and from
-the trained network's warm start on held-out 512x512 grids, `dual_reuse` from
-a cold start and from the previous frame's dual over a sequence of edited
-grids (both outside the timed steps).  `cpu_baseline` times the CPU oracle (FP64, one thread) on a bounded
-number of iterations of the same problem, and checks the GPU cut against the
-oracle's max-flow energy.
+steps (voxels x chain families x sweep launches / wall time).  `roofline`
+rates the dominant kernel, the three-family sweep launch, by its event-timed
+launches (HIP events on the solve's stream, in the last timed step) against
+HBM bandwidth: 36 algorithmic bytes per voxel per launch (z_j, a_j read and
+q_j written for each family) plus 12 on the launches that write edge duals.
+`traffic` is the counter-measured HBM bytes per launch from the committed
+profile, reported only while the sweep sources match the profile's hash.
+Other objects: the 1024x1024 image (two-set form) with its own roofline, the
+learned warm start and dual reuse (time to the exact cut, cold against warm),
+the 8-connected image, alpha-expansion, the mixed BCD loop, and the batched
+solve of 64 uneven grids.  `cpu_baseline` times the CPU oracle (FP64) on a
+bounded number of iterations of the same volume, on one thread and on all the
+host's threads, and checks the GPU cut against the oracle's max-flow energy.
 """
 import argparse
 import json
@@ -29,9 +34,13 @@ if ROOT not in sys.path:
 
 METRIC = "chain-prox voxel-sweeps/s (%HBM peak); time-to-exact-cut cold vs warm start"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_VOXEL_SWEEP = 16.0  # two-set DR: 32 B per voxel-iteration over two sweeps
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "image2d_1024_sweep_traffic.md")
-SWEEP_SOURCES = ["chain.hpp", "piece.hpp", "sweeps.hip", "launch.hpp"]
+VOL_BYTES_VALUE = 36.0  # per voxel and sweep launch of the three families (values only)
+VOL_BYTES_DUALS = 12.0  # added on the launches that also write the edge duals
+IMG_BYTES_PER_VOXEL_SWEEP = 16.0  # two-set DR: 32 B per voxel-iteration over two sweeps
+IMG_BYTES_DUALS = 4.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "volume3d_256x256x128_sweep_traffic.md")
+IMG_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "image2d_1024_sweep_traffic.md")
+SWEEP_SOURCES = ["chain.hpp", "lean.hpp", "piece.hpp", "sweeps.hip", "launch.hpp"]
 
 
 def sweep_sources_hash():
@@ -45,12 +54,12 @@ def sweep_sources_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed counter summary, or None
+def measured_traffic(path=TRAFFIC_PROFILE):
+    """HBM bytes per sweep launch from a committed counter summary, or None
     when the sweep kernels changed since the counters were taken."""
     import re
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(path).read()
     except OSError:
         return None
     m_hash = re.search(r"sweep sources sha256\[:16\]: `([0-9a-f]+)`", text)
@@ -66,19 +75,22 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--check-every", type=int, default=4)
-    ap.add_argument("--seed", type=int, default=2000)
-    ap.add_argument("--size", type=int, default=1024)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="approximate CPU time budget of the oracle baseline sample")
+    ap.add_argument("--seed", type=int, default=3000, help="seed of the volume")
+    ap.add_argument("--image-seed", type=int, default=2000)
+    ap.add_argument("--size", type=int, default=1024, help="side of the image workload")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="approximate CPU time of each oracle baseline leg (one thread, all threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also run the all-core oracle to its certificate on the volume (minutes)")
     ap.add_argument("--warm-grids", type=int, default=16,
                     help="held-out 512x512 grids for the cold vs warm-start comparison (0: skip)")
+    ap.add_argument("--no-image", dest="image", action="store_false",
+                    help="skip the 1024x1024 image section")
     ap.add_argument("--no-grid8", dest="grid8", action="store_false",
-                    help="skip the 8-connected version of the workload")
+                    help="skip the 8-connected version of the image")
     ap.add_argument("--no-multilabel", dest="multilabel", action="store_false",
                     help="skip the alpha-expansion (multi-label) section")
-    ap.add_argument("--no-volume", dest="volume", action="store_false",
-                    help="skip the 256x256x128 volume section")
     ap.add_argument("--no-batched", dest="batched", action="store_false",
                     help="skip the section solving 64 uneven grids in one batch")
     ap.add_argument("--no-mixed", dest="mixed", action="store_false",
@@ -89,33 +101,126 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(w, a, gpu_energy, budget_s):
-    """Oracle (FP64, single thread) on a bounded sample of the same problem."""
-    import numpy as np
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return os.cpu_count(), model
 
+
+def cpu_threads():
+    """Threads of the all-core leg: OMP_NUM_THREADS when set (the host's
+    share), else every CPU the process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(w, a, gpu_res, budget_s, full=False):
+    """The oracle (FP64 product-space DR, unchanged) on a bounded number of
+    iterations of the same volume, on one thread and on all threads, plus
+    its max-flow energy for the exactness check."""
     import oracle
     oracle.build(force=False)
     n = w.size
-    t0 = time.perf_counter()
-    oracle.dr_solve(w, a, max_iters=2, gap_tol=0)
-    per_iter = (time.perf_counter() - t0) / 2
-    iters = max(2, min(400, int(budget_s / max(per_iter, 1e-6))))
-    t0 = time.perf_counter()
-    r = oracle.dr_solve(w, a, max_iters=iters, gap_tol=0)
-    dt = time.perf_counter() - t0
+    r = w.ndim
+    nproc, model = cpu_info()
+    threads = cpu_threads()
+    legs = {}
+    for name, th in (("single_thread", 1), ("all_threads", threads)):
+        t0 = time.perf_counter()
+        oracle.dr_solve(w, a, max_iters=1, gap_tol=0, threads=th)
+        per_iter = time.perf_counter() - t0
+        iters = max(1, min(60, int(budget_s / max(per_iter, 1e-6))))
+        t0 = time.perf_counter()
+        res = oracle.dr_solve(w, a, max_iters=iters, gap_tol=0, threads=th)
+        dt = time.perf_counter() - t0
+        legs[name] = {"threads": oracle.threads_used(th), "iters": res["iters"], "seconds": dt,
+                      "voxel_sweeps_per_s": n * r * res["iters"] / dt, "ms_per_iter": 1e3 * dt / res["iters"]}
     t0 = time.perf_counter()
     e_star, _, _ = oracle.mincut(w, a, "dinic")
     dt_flow = time.perf_counter() - t0
-    return {
-        "value": n * 2 * r["iters"] / dt,
+    allc = legs["all_threads"]
+    out = {
+        "value": allc["voxel_sweeps_per_s"],
         "unit": "voxel-sweeps/s",
-        "cores": 1,
+        "cores": allc["threads"],
         "kind": "oracle",
-        "sample": "FP64 two-set DR, %d iterations on the same 1024x1024 grid (%.1f s); "
-                  "Dinic max-flow %.2f s" % (r["iters"], dt, dt_flow),
+        "sample": "FP64 product-space DR (certificate every iteration) on the same 256x256x128 volume: "
+                  "%d iterations on %d threads (%.1f s), %d on one thread (%.1f s); Dinic max-flow %.1f s"
+                  % (allc["iters"], allc["threads"], allc["seconds"], legs["single_thread"]["iters"],
+                     legs["single_thread"]["seconds"], dt_flow),
+        "single_thread": legs["single_thread"],
+        "all_threads": allc,
+        "nproc": nproc,
+        "cpu_model": model,
         "maxflow_energy": e_star,
-        "gpu_energy_exact": bool(gpu_energy == e_star),
-        "oracle_ms_per_iter": 1e3 * dt / r["iters"],
+        "maxflow_seconds": dt_flow,
+        "gpu_energy_exact": bool(gpu_res.energy == e_star),
+        "to_certificate_estimate_s": gpu_res.iters * allc["ms_per_iter"] / 1e3,
+        "to_certificate_note": "the oracle runs the same iteration; estimate = GPU iterations to the "
+                               "certificate x all-thread seconds per oracle iteration",
+    }
+    if full:
+        t0 = time.perf_counter()
+        res = oracle.dr_solve(w, a, max_iters=3000, gap_tol=1e-3, threads=threads)
+        out["to_certificate"] = {"iters": res["iters"], "seconds": time.perf_counter() - t0,
+                                 "threads": allc["threads"], "certified": res["status"] == 0,
+                                 "energy": res["energy"]}
+    return out
+
+
+def timed_solves(wt, at, steps, warmup, check_every):
+    """`warmup` untimed solves, then `steps` timed ones (the last with per-launch
+    events); returns (results, wall seconds of the timed region, per-step walls)."""
+    import torch
+
+    from paper_1503_01563_amd import mc
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        mc.tv_solve(wt, at, max_iters=3000, check_every=check_every)
+    torch.cuda.synchronize()
+    results, walls = [], []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ts = time.perf_counter()
+        results.append(mc.tv_solve(wt, at, max_iters=3000, check_every=check_every, profile=k == steps - 1))
+        walls.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    return results, time.perf_counter() - t0, walls
+
+
+def roofline(prof, n, bytes_value, bytes_duals, kernel, traffic, dual_launches_per_check=1):
+    """Rate of the sweep launches of one profiled solve: algorithmic bytes of
+    its launches (the first `checks` of them also write duals) over their
+    event-timed device time."""
+    launches = max(prof.sweep_launches, 1)
+    dual_launches = min(prof.checks * dual_launches_per_check, launches)
+    total_bytes = n * (bytes_value * launches + bytes_duals * dual_launches)
+    seconds = prof.sweep_ms / 1e3
+    achieved = total_bytes / seconds / 1e9
+    return {
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per value launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+        "kernel": kernel,
+        "avg_launch_us": 1e6 * seconds / launches,
+        "bytes_per_launch": total_bytes / launches,
+        "launches": prof.sweep_launches,
+        "dual_launches": dual_launches,
     }
 
 
@@ -128,32 +233,15 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1503_01563_amd import gen, mc
+    from paper_1503_01563_amd import gen
 
     dev = torch.device("cuda:0")
-    shape = (args.size, args.size)
-    w, a = gen.config_image2d(args.seed, shape=shape)
+    w, a = gen.config_volume3d(args.seed)
     wt = torch.from_numpy(w).to(dev)
     at = [torch.from_numpy(x).to(dev) for x in a]
     n = w.size
-    r = 2
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        mc.tv_solve(wt, at, max_iters=2000, check_every=args.check_every)
-    torch.cuda.synchronize()
-    # Every timed step is one full cold-start solve.  The last one also times
-    # each sweep launch with a pair of HIP events on the solve's stream (for the
-    # roofline); the event records add about 7 us of stream time per launch, so
-    # the other steps run without them.
-    results, walls = [], []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        ts = time.perf_counter()
-        results.append(mc.tv_solve(wt, at, max_iters=2000, check_every=args.check_every,
-                                   profile=k == args.steps - 1))
-        walls.append(time.perf_counter() - ts)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    r = w.ndim
+    results, dt, walls = timed_solves(wt, at, args.steps, args.warmup, args.check_every)
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -161,12 +249,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    sweeps = sum(n * res.sweep_launches for res in results)  # sweeps actually run
-    timed = results[-1]  # the step whose sweep launches carry events
-    avg_launch_s = timed.sweep_ms / 1e3 / max(timed.sweep_launches, 1)
-    bytes_per_launch = n * BYTES_PER_VOXEL_SWEEP
-    achieved = bytes_per_launch / avg_launch_s / 1e9
-    last = results[-1]
+    sweeps = sum(r * n * res.sweep_launches for res in results)  # voxel-sweeps actually run
+    last = results[-1]  # the step whose sweep launches carry events
     out = {
         "metric": METRIC,
         "value": sweeps / dt,
@@ -181,45 +265,66 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "image2d %dx%d 4-connected, noisy ellipses, lambda=2, dyadic 2^-8, seed %d"
-                        % (shape[0], shape[1], args.seed),
-            "solver": "two-set Douglas-Rachford, cold start, certificate every %d iterations"
+            "workload": "volume %dx%dx%d (WxHxD) 6-connected, noisy ellipsoids, lambda=1.5, dyadic 2^-8, seed %d"
+                        % (w.shape[2], w.shape[1], w.shape[0], args.seed),
+            "solver": "product-space Douglas-Rachford (r = 3), cold start, certificate every %d iterations"
                       % args.check_every,
             "stop": "certificate < 1e-3",
         },
         "time_to_exact_cut_ms": 1e3 * float(np.median(walls)),
+        "device_ms_median": float(np.median([q.ms for q in results])),
         "iters": last.iters,
         "certified": all(res.converged for res in results),
         "energy": last.energy,
-        "roofline": {
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
-            "kernel": "k_sweep<ModeRows2> + k_sweep<ModeCols2> (chain-prox sweeps)",
-            "avg_launch_us": 1e6 * avg_launch_s,
-            "bytes_per_launch": bytes_per_launch,
-        },
+        "roofline": roofline(last, n, VOL_BYTES_VALUE, VOL_BYTES_DUALS,
+                             "k_sweep_triple (rows, columns and depth chains of the volume in one launch)",
+                             measured_traffic(TRAFFIC_PROFILE)),
     }
+    if args.image:
+        out["image2d"] = image2d_section(args.image_seed, (args.size, args.size), args.check_every)
     if args.warm_grids > 0:
         out["warm_start"] = warm_start_section(args.warm_grids)
         out["dual_reuse"] = dual_reuse_section()
     if args.grid8:
-        out["grid8"] = grid8_section(args.seed, shape)
+        out["grid8"] = grid8_section(args.image_seed, (args.size, args.size))
     if args.multilabel:
         out["alpha_expansion"] = alpha_expansion_section()
     if args.mixed:
-        out["mixed_outer_loop"] = mixed_outer_loop_section(args.seed)
-    if args.volume:
-        out["volume"] = volume_section()
+        out["mixed_outer_loop"] = mixed_outer_loop_section(args.image_seed)
     if args.batched:
         out["batched"] = batched_section()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, a, last.energy, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, a, last, args.cpu_seconds, full=args.cpu_full)
     print(json.dumps(out))
+
+
+def image2d_section(seed, shape, check_every, steps=5):
+    """The 1024x1024 segmentation-shaped image in the two-set form: time to the
+    exact cut and the rate of its row and column sweep launches."""
+    import numpy as np
+    import torch
+
+    from paper_1503_01563_amd import gen
+    dev = torch.device("cuda:0")
+    w, a = gen.config_image2d(seed, shape=shape)
+    wt = torch.from_numpy(w).to(dev)
+    at = [torch.from_numpy(x).to(dev) for x in a]
+    results, dt, walls = timed_solves(wt, at, steps, 1, check_every)
+    last = results[-1]
+    n = w.size
+    return {
+        "workload": "image2d %dx%d 4-connected, noisy ellipses, lambda=2, dyadic 2^-8, seed %d"
+                    % (shape[0], shape[1], seed),
+        "solver": "two-set Douglas-Rachford, cold start, certificate every %d iterations" % check_every,
+        "time_to_exact_cut_ms": 1e3 * float(np.median(walls)),
+        "iters": last.iters,
+        "certified": all(q.converged for q in results),
+        "energy": last.energy,
+        "voxel_sweeps_per_s": sum(n * q.sweep_launches for q in results) / dt,
+        "roofline": roofline(last, n, IMG_BYTES_PER_VOXEL_SWEEP, IMG_BYTES_DUALS,
+                             "k_sweep<ModeRows2> + k_sweep<ModeCols2> (row and column sweeps)",
+                             measured_traffic(IMG_TRAFFIC_PROFILE), dual_launches_per_check=2),
+    }
 
 
 def grid8_section(seed, shape, repeats=3):
@@ -335,39 +440,6 @@ def mixed_outer_loop_section(seed=2000, repeats=3):
                           "certified": res.converged, "energy": res.energy}
         out[name] = row
     return out
-
-
-def volume_section(seed=3000, repeats=3):
-    """The 6-connected 256x256x128 volume (W x H x D) in the product space
-    (r = 3): time to the exact cut, and the rate of its sweep launches (all
-    three families in one launch, 36 algorithmic bytes per voxel: z_j and a_j
-    read, q_j written, for each family; the averaging step is a kernel of its
-    own)."""
-    import numpy as np
-    import torch
-
-    from paper_1503_01563_amd import gen, mc
-    dev = torch.device("cuda:0")
-    w, a = gen.config_volume3d(seed)
-    wt = torch.from_numpy(w).to(dev)
-    at = [torch.from_numpy(x).to(dev) for x in a]
-    mc.tv_solve(wt, at, max_iters=3000, check_every=4)
-    runs = [mc.tv_solve(wt, at, max_iters=3000, check_every=4) for _ in range(repeats)]
-    prof = mc.tv_solve(wt, at, max_iters=3000, check_every=4, profile=True)  # per-launch events, untimed
-    launch_s = 1e-3 * prof.sweep_ms / max(1, prof.sweep_launches)
-    r = runs[-1]
-    return {
-        "workload": "volume %dx%dx%d (WxHxD) 6-connected, noisy ellipsoids, lambda=1.5, seed %d"
-                    % (w.shape[2], w.shape[1], w.shape[0], seed),
-        "solver": "product-space Douglas-Rachford (r = 3), certificate every 4 iterations",
-        "time_to_exact_cut_ms": float(np.median([q.ms for q in runs])),
-        "iters": r.iters,
-        "certified": r.converged,
-        "energy": r.energy,
-        "sweep_launch_us": 1e6 * launch_s,
-        "sweep_voxel_sweeps_per_s": 3 * w.size / launch_s,
-        "sweep_algorithmic_gbs": 36.0 * w.size / launch_s / 1e9,
-    }
 
 
 def batched_section(seed=4000, count=64, repeats=3):

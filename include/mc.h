@@ -42,7 +42,7 @@
  * Threading.  One context per host thread; a context is bound to the device
  * it was created on.  Identical inputs give identical outputs (all
  * reductions use fixed trees; no floating-point atomics).  Batched solves
- * choose their work-item count by timing unless opts->reserved[0] fixes it;
+ * choose their work-item count by timing unless opts->batch_items fixes it;
  * the choice is cached per context, and a different count can change the
  * last bits of the iterates (never the certified energies).
  */
@@ -91,7 +91,7 @@ extern "C" {
 #define MC_VARIANT_BCD 3         /* cyclic projections / block coordinate descent (Sec. 4.1) */
 #define MC_VARIANT_AP 4          /* alternating projections in the product space (Sec. 4.2) */
 #define MC_VARIANT_FISTA 5       /* FISTA on the smooth dual, step 1/r (Sec. 4.1) */
-/* Block coordinate descent for up to opts->reserved[1] iterations (0 = 16),
+/* Block coordinate descent for up to opts->bcd_iters iterations (0 = 16),
  * then, unless it certified, the splitting of MC_VARIANT_AUTO started from its
  * dual blocks y and primal x = -w - sum_j y_j (two-set form: z0 = x + y_rows;
  * product space: z0_j = y_j + x / r).  BCD certifies within tens of iterations
@@ -116,8 +116,9 @@ typedef struct {
                              1e-3, 0, -1e-3, -1e-2, -1e-1, -1); the first of least energy
                              is returned (default 1e-3) */
     uint32_t flags;       /* MC_VALIDATE | MC_PROFILE | MC_WARM_MOVES | MC_WHOLE_CHAINS | MC_PIECE_CHAINS */
-    int32_t reserved[4];  /* reserved[0]: work items per sweep launch of batched solves (0 = tuned);
-                             reserved[1]: BCD iterations of MC_VARIANT_BCD_DR (0 = 16) */
+    int32_t batch_items;  /* mc_tv_solve_batched: work items per sweep launch (0 = tuned) */
+    int32_t bcd_iters;    /* MC_VARIANT_BCD_DR: block coordinate descent iterations (0 = 16) */
+    int32_t reserved[2];  /* must be 0 */
 } mc_opts;
 
 typedef struct {
@@ -222,7 +223,11 @@ int mc_cut_energy(mc_ctx *ctx, const mc_grid *grid, const float *w,
 
 /*
  * mc_tv_solve_batched -- minimum cuts of n_grids 2D grids of possibly different
- * sizes, solved together (two-set form).  Arrays are per grid:
+ * sizes, solved together (two-set form, Sec. 3.3 special case r = 2).  The
+ * paper runs the chain proxes of a family in parallel over chains
+ * (Sec. 5.1); here every sweep launch covers the chains of all unfinished
+ * grids at once, and each grid stops at its own certificate (Sec. 2.2).
+ * Arrays are per grid:
  *   grids[g]       2D grid {H, W}.
  *   w[g]           [n_g] unaries (device).
  *   a[2g], a[2g+1] [n_g] weights along W and along H (device).
@@ -231,7 +236,7 @@ int mc_cut_energy(mc_ctx *ctx, const mc_grid *grid, const float *w,
  *   stats[g]       host; ms is the device time from the start of the solve to
  *                  the check that certified the grid (per-grid solve time).
  * opts.check_every is rounded up to an even number of iterations: one check
- * period is captured in a hipGraph and replayed.  opts.reserved[0] > 0 fixes
+ * period is captured in a hipGraph and replayed.  opts.batch_items > 0 fixes
  * the work items per sweep launch; 0 uses the value tuned on the first solve
  * of this batch shape.  Synchronises the stream.  Returns MC_OK when every
  * grid is certified, MC_NOT_CONVERGED otherwise.

@@ -25,17 +25,27 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
+_LIB_OMP = os.path.join(_HERE, "liborc_omp.so")
 _lib = None
+_lib_omp = None
+
+_CFLAGS = ["-O2", "-fPIC", "-shared", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra"]
+
+
+def _compile(out, extra):
+    tmp = out + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc"] + _CFLAGS + extra + ["-o", tmp, _SRC, "-lm"], check=True)
+    os.replace(tmp, out)
 
 
 def build(force: bool = True) -> str:
-    """Compile oracle.c with gcc into liborc.so (plain IEEE FP64, no contraction)."""
+    """Compile oracle.c with gcc (plain IEEE FP64, no contraction): liborc.so on
+    one thread, and liborc_omp.so, the same source with OpenMP (the all-core
+    CPU baseline; identical results)."""
     if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-ffp-contract=off",
-               "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
-        subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
+        _compile(_LIB, ["-Wno-unknown-pragmas"])
+    if force or not os.path.exists(_LIB_OMP):
+        _compile(_LIB_OMP, ["-fopenmp"])
     return _LIB
 
 
@@ -46,31 +56,51 @@ class OrcStats(ctypes.Structure):
                 ("tau_used", ctypes.c_double)]
 
 
-def _load():
-    global _lib
+def _load(threads: int = 1):
+    """The plain library, or with threads > 1 the OpenMP build set to that
+    many threads."""
+    global _lib, _lib_omp
+    if threads > 1:
+        if _lib_omp is None:
+            if not os.path.exists(_LIB_OMP):
+                build(force=False)
+            _lib_omp = _declare(ctypes.CDLL(_LIB_OMP))
+        _lib_omp.orc_set_threads(int(threads))
+        return _lib_omp
     if _lib is None:
         if not os.path.exists(_LIB):
-            build()
-        lib = ctypes.CDLL(_LIB)
-        P = ctypes.c_void_p
-        lib.orc_tv1d.argtypes = [ctypes.c_long, P, P, P, P]
-        lib.orc_tv1d.restype = ctypes.c_int
-        lib.orc_cut_energy.argtypes = [ctypes.c_int, P, P, P, P]
-        lib.orc_cut_energy.restype = ctypes.c_double
-        lib.orc_bruteforce.argtypes = [ctypes.c_int, P, P, P, P, P, P]
-        lib.orc_bruteforce.restype = ctypes.c_double
-        lib.orc_mincut.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
-        lib.orc_mincut.restype = ctypes.c_double
-        lib.orc_dr_solve.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_int,
-                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                     P, P, P, P, P, P, ctypes.POINTER(OrcStats)]
-        lib.orc_dr_solve.restype = ctypes.c_int
-        lib.orc_prox_family.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, P, P]
-        lib.orc_prox_family.restype = ctypes.c_int
-        lib.orc_lower_bound.argtypes = [ctypes.c_int, P, P, P, P, P, P]
-        lib.orc_lower_bound.restype = ctypes.c_int
-        _lib = lib
+            build(force=False)
+        _lib = _declare(ctypes.CDLL(_LIB))
     return _lib
+
+
+def threads_used(threads: int) -> int:
+    """Threads the OpenMP build runs with after asking for `threads`."""
+    return int(_load(max(2, threads)).orc_set_threads(0)) if threads > 1 else 1
+
+
+def _declare(lib):
+    """argtypes of every exported function."""
+    P = ctypes.c_void_p
+    lib.orc_tv1d.argtypes = [ctypes.c_long, P, P, P, P]
+    lib.orc_tv1d.restype = ctypes.c_int
+    lib.orc_cut_energy.argtypes = [ctypes.c_int, P, P, P, P]
+    lib.orc_cut_energy.restype = ctypes.c_double
+    lib.orc_bruteforce.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+    lib.orc_bruteforce.restype = ctypes.c_double
+    lib.orc_mincut.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, P, P, P]
+    lib.orc_mincut.restype = ctypes.c_double
+    lib.orc_dr_solve.argtypes = [ctypes.c_int, P, P, P, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 P, P, P, P, P, P, ctypes.POINTER(OrcStats)]
+    lib.orc_dr_solve.restype = ctypes.c_int
+    lib.orc_prox_family.argtypes = [ctypes.c_int, P, ctypes.c_int, P, P, P, P]
+    lib.orc_prox_family.restype = ctypes.c_int
+    lib.orc_lower_bound.argtypes = [ctypes.c_int, P, P, P, P, P, P]
+    lib.orc_lower_bound.restype = ctypes.c_int
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_threads.restype = ctypes.c_int
+    return lib
 
 
 def _f64(x):
@@ -177,13 +207,14 @@ def lower_bound(w, a, p):
 
 
 def dr_solve(w, a, variant=None, max_iters=500, gap_tol=1e-3, tv_tol=0.0, tau0=1e-3,
-             z0=None, history=False, return_z=False):
+             z0=None, history=False, return_z=False, threads=1):
     """FP64 Douglas-Rachford (averaged alternating reflections).
 
     variant 0 = two-set form (2D only), 1 = product space.  Default: 0 for 2D,
-    1 for 3D.  Returns a dict with x, labels, stats (and histories / z).
+    1 for 3D.  threads > 1 runs the OpenMP build (same results).  Returns a
+    dict with x, labels, stats (and histories / z).
     """
-    lib = _load()
+    lib = _load(threads)
     w = _f64(w)
     nd = w.ndim
     if variant is None:

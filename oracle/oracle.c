@@ -19,6 +19,12 @@
  *   (Sec. 2.3, eq. (TV)).
  *
  * Parity status of each function is listed in its comment.
+ *
+ * Threads.  Built plainly (liborc.so) everything runs on one thread.  Built
+ * with -fopenmp (liborc_omp.so, the benchmark's all-core baseline) the chains
+ * of a family, the elementwise updates and the nine threshold energies of a
+ * certificate are spread over threads; every sum keeps its serial order, so
+ * both builds return identical bits.
  */
 #include <math.h>
 #include <stdint.h>
@@ -464,24 +470,35 @@ static int orc_project_family(const orc_grid *g, int axis, const double *a_axis,
 {
     long L = orc_extent(g, axis), st = orc_stride(g, axis);
     long nc = orc_nchains(g, axis);
-    double *cv = (double *)malloc(sizeof(double) * (size_t)L);
-    double *ca = (double *)malloc(sizeof(double) * (size_t)(L > 1 ? L - 1 : 1));
-    double *cx = (double *)malloc(sizeof(double) * (size_t)L);
-    double *cp = (double *)malloc(sizeof(double) * (size_t)(L > 1 ? L - 1 : 1));
-    if (!cv || !ca || !cx || !cp) { free(cv); free(ca); free(cx); free(cp); return ORC_ERR_NOMEM; }
-    for (long c = 0; c < nc; ++c) {
-        long b = orc_chain_base(g, axis, c);
-        for (long k = 0; k < L; ++k) cv[k] = v[b + k * st];
-        for (long k = 0; k + 1 < L; ++k) ca[k] = a_axis[b + k * st];
-        orc_tv1d(L, cv, ca, cx, cp);
-        for (long k = 0; k < L; ++k) y[b + k * st] = cv[k] - cx[k];
-        if (p) {
-            for (long k = 0; k + 1 < L; ++k) p[b + k * st] = cp[k];
-            p[b + (L - 1) * st] = 0.0;
+    int rc = ORC_OK;
+#pragma omp parallel
+    {
+        /* one set of chain buffers per thread */
+        double *cv = (double *)malloc(sizeof(double) * (size_t)L);
+        double *ca = (double *)malloc(sizeof(double) * (size_t)(L > 1 ? L - 1 : 1));
+        double *cx = (double *)malloc(sizeof(double) * (size_t)L);
+        double *cp = (double *)malloc(sizeof(double) * (size_t)(L > 1 ? L - 1 : 1));
+        int ok = cv && ca && cx && cp;
+        if (!ok) {
+#pragma omp atomic write
+            rc = ORC_ERR_NOMEM;
         }
+#pragma omp for schedule(static)
+        for (long c = 0; c < nc; ++c) {
+            if (!ok) continue;
+            long b = orc_chain_base(g, axis, c);
+            for (long k = 0; k < L; ++k) cv[k] = v[b + k * st];
+            for (long k = 0; k + 1 < L; ++k) ca[k] = a_axis[b + k * st];
+            orc_tv1d(L, cv, ca, cx, cp);
+            for (long k = 0; k < L; ++k) y[b + k * st] = cv[k] - cx[k];
+            if (p) {
+                for (long k = 0; k + 1 < L; ++k) p[b + k * st] = cp[k];
+                p[b + (L - 1) * st] = 0.0;
+            }
+        }
+        free(cv); free(ca); free(cx); free(cp);
     }
-    free(cv); free(ca); free(cx); free(cp);
-    return ORC_OK;
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -593,9 +610,8 @@ int orc_dr_solve(int ndim, const long *dims, const double *w,
     double *tmp = (double *)malloc(sizeof(double) * (size_t)nz);
     double *tmp2 = (double *)malloc(sizeof(double) * (size_t)n);
     double *x = (double *)malloc(sizeof(double) * (size_t)n);
-    uint8_t *lab = (uint8_t *)malloc((size_t)n);
     uint8_t *best_lab = (uint8_t *)malloc((size_t)n);
-    if (!u || !z || !y || !pd || !tmp || !tmp2 || !x || !lab || !best_lab) return ORC_ERR_NOMEM;
+    if (!u || !z || !y || !pd || !tmp || !tmp2 || !x || !best_lab) return ORC_ERR_NOMEM;
     for (long i = 0; i < n; ++i) u[i] = -w[i];
     if (z0) memcpy(z, z0, sizeof(double) * (size_t)nz);
     double *pj[3] = {pd, pd + n, pd + 2 * n};
@@ -609,9 +625,12 @@ int orc_dr_solve(int ndim, const long *dims, const double *w,
         if (variant == 0) {
             double *y1 = y, *y2 = y + n;
             orc_project_family(&g, 0, a[0], z, y1, pj[0]);            /* Pi_A(z) */
+#pragma omp parallel for schedule(static)
             for (long i = 0; i < n; ++i) tmp[i] = 2.0 * y1[i] - z[i]; /* R_A z */
+#pragma omp parallel for schedule(static)
             for (long i = 0; i < n; ++i) tmp2[i] = u[i] - tmp[i];
             orc_project_family(&g, 1, a[1], tmp2, y2, pj[1]);         /* Pi_{K2}(u - R_A z) */
+#pragma omp parallel for schedule(static)
             for (long i = 0; i < n; ++i) {
                 double pib = u[i] - y2[i];                             /* Pi_B(R_A z) */
                 double rb = 2.0 * pib - tmp[i];                        /* R_B R_A z */
@@ -621,6 +640,7 @@ int orc_dr_solve(int ndim, const long *dims, const double *w,
         } else {
             for (int j = 0; j < r; ++j)
                 orc_project_family(&g, j, a[j], z + (long)j * n, y + (long)j * n, pj[j]);
+#pragma omp parallel for schedule(static)
             for (long i = 0; i < n; ++i) {
                 double srk = 0.0;
                 for (int j = 0; j < r; ++j) {
@@ -640,16 +660,26 @@ int orc_dr_solve(int ndim, const long *dims, const double *w,
             }
         }
         orc_certificate(&g, w, a, pj, &lb, &tvgap);
-        energy = INFINITY;
+        /* E(S_t) for every threshold (independent), then the first of least energy */
+        double e_t[ORC_NTAU];
+#pragma omp parallel for schedule(dynamic)
         for (int t = 0; t < ORC_NTAU; ++t) {
-            for (long i = 0; i < n; ++i) lab[i] = (uint8_t)(x[i] > taus[t]);
-            double e = orc_cut_energy(ndim, dims, w, a, lab);
-            if (e < energy) {
-                energy = e;
+            uint8_t *lt = (uint8_t *)malloc((size_t)n);
+            if (!lt) { e_t[t] = NAN; continue; }
+            for (long i = 0; i < n; ++i) lt[i] = (uint8_t)(x[i] > taus[t]);
+            e_t[t] = orc_cut_energy(ndim, dims, w, a, lt);
+            free(lt);
+        }
+        energy = INFINITY;
+        int t_best = 0;
+        for (int t = 0; t < ORC_NTAU; ++t) {
+            if (e_t[t] < energy) {
+                energy = e_t[t];
                 tau_used = taus[t];
-                memcpy(best_lab, lab, (size_t)n);
+                t_best = t;
             }
         }
+        for (long i = 0; i < n; ++i) best_lab[i] = (uint8_t)(x[i] > taus[t_best]);
         cert = energy - lb;
         if (cert_hist) cert_hist[it - 1] = cert;
         if (tvgap_hist) tvgap_hist[it - 1] = tvgap;
@@ -670,8 +700,25 @@ int orc_dr_solve(int ndim, const long *dims, const double *w,
         st->tau_used = tau_used;
     }
     free(u); free(z); free(y); free(pd); free(tmp); free(tmp2); free(x);
-    free(lab); free(best_lab);
+    free(best_lab);
     return ORC_OK;
+}
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the OpenMP build (no effect in the plain build); returns the
+ * number the next parallel region will use. */
+int orc_set_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+    return omp_get_max_threads();
+#else
+    (void)k;
+    return 1;
+#endif
 }
 
 /* Projection onto one family, exposed for tests (x = prox, p = edge duals). */

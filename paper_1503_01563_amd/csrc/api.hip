@@ -749,7 +749,7 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
         return solve_variant(c, g, w, a, z0, x_out, labels_out, z_out, stats, o, (hipStream_t)stream);
     if (o.variant == MC_VARIANT_BCD_DR) {
         if (z0 || z_out) return fail(MC_ERR_INVALID_ARG, "MC_VARIANT_BCD_DR takes no z0 / z_out");
-        const int k = o.reserved[1] > 0 ? o.reserved[1] : 16;
+        const int k = o.bcd_iters > 0 ? o.bcd_iters : 16;
         hipStream_t s = (hipStream_t)stream;
         mc_opts ob = o;
         ob.variant = MC_VARIANT_BCD;

@@ -240,7 +240,7 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
         MC_HIP(hipMemsetAsync(pl.tab[gi].z[0], 0, sizeof(float) * (size_t)geos[gi].n, s));
 
     const unsigned long long sig = signature(geos);
-    int items = o.reserved[0] > 0 ? o.reserved[0] : 0;
+    int items = o.batch_items > 0 ? o.batch_items : 0;
     auto it_tuned = c->tuned_items.find(sig);
     if (items == 0 && it_tuned != c->tuned_items.end()) items = it_tuned->second;
 

@@ -1,4 +1,5 @@
-// launch.hpp -- host-side launchers for the libmc kernels (kernels.hip).
+// launch.hpp -- host-side launchers of the libmc kernels (sweeps.hip, reduce.hip,
+// batch.hip, grid8.hip, variants.hip, multilabel.hip) and the structs they share.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -51,7 +51,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("max_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("gap_tol", ctypes.c_double), ("variant", ctypes.c_int32),
                 ("tau0", ctypes.c_float), ("flags", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("batch_items", ctypes.c_int32), ("bcd_iters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Stats(ctypes.Structure):
@@ -378,7 +379,7 @@ def tv_solve_batched(ws: Sequence[torch.Tensor], As: Sequence[Sequence[torch.Ten
             xp[g] = x.data_ptr()
     st = (Stats * ng)()
     o = make_opts(max_iters, check_every, gap_tol, VARIANT_AUTO, tau0)
-    o.reserved[0] = int(items)
+    o.batch_items = int(items)
     rc = lib.mc_tv_solve_batched(context(dev), ng, grids, ctypes.cast(wp, ctypes.c_void_p),
                                  ctypes.cast(ap, ctypes.c_void_p), ctypes.cast(lp, ctypes.c_void_p),
                                  ctypes.cast(xp, ctypes.c_void_p) if return_x else None,

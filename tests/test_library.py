@@ -79,6 +79,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(mc.Opts) == 48
     assert ctypes.sizeof(mc.Stats) == 72
     assert mc.Stats.ms.offset == 44 and mc.Opts.flags.offset == 24
+    assert mc.Opts.batch_items.offset == 28 and mc.Opts.bcd_iters.offset == 32 and mc.Opts.reserved.offset == 36
     assert ctypes.sizeof(mc.MLStats) == 56
     assert (mc.MLStats.dr_iters.offset, mc.MLStats.energy0.offset, mc.MLStats.energy.offset,
             mc.MLStats.ms.offset) == (24, 32, 40, 48)
