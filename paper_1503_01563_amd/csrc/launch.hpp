@@ -39,7 +39,7 @@ struct PieceCfg {
 // Pieces for a family: about `want` work items (16 to 64 positions per piece).
 // launch_items is the number of work items of the whole launch the family is
 // part of (0: this family alone); launches of at most kLatencyItems items run
-// about one wave per SIMD and get a longer overlap (24 instead of 8), so that
+// about one wave per SIMD and get a longer overlap (12 instead of 8), so that
 // almost no piece has to restart its scans.
 PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items);
 constexpr int kDefaultItems = 4096;

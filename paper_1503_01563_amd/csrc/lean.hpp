@@ -125,8 +125,8 @@ __host__ __device__ inline bool lean_step(LeanScan& S, int m, float vk, float ak
 // chain.hpp); each only advances while its last knot is not ahead of the
 // other's, and the first knot both emit (same position, same side) is a knot
 // of the true solution.  If that knot lies before b0, U stops and L goes on
-// alone, exact from there; otherwise the lane restarts with a four times
-// longer overlap (from the chain start the dual is 0 and L alone is exact).
+// alone, exact from there; otherwise the lane restarts with a twice longer
+// overlap (from the chain start the dual is 0 and L alone is exact).
 struct LeanLane {
     int m, b0, b1, W;
     bool bracket;   // L and U both running
@@ -167,31 +167,31 @@ struct LeanLane {
         if (!active) L.on = U.on = false;
     }
 
+    // Whether each scan takes a step this iteration: both decided from the
+    // knots at the start of the iteration (a scan whose last knot is ahead of
+    // the other's waits; deciding before either steps only makes a scan wait
+    // one iteration longer, and keeps the two steps independent of each other).
     __host__ __device__ inline bool steps_l() const { return scanning && !(bracket && lastL > lastU); }
     __host__ __device__ inline bool needs_u() const { return scanning && bracket && lastU <= lastL; }
-    // positions the next step_l / step_u read (`idle` when the step will not
-    // read).  Both are read before step_l, which can change whether U steps,
-    // so U's position is read whenever it brackets.
-    __host__ __device__ inline int l_pos(int idle) const { return steps_l() ? L.k : idle; }
-    __host__ __device__ inline int u_pos(int idle) const { return scanning && bracket ? U.k : idle; }
 
-    // Advance L; vk, ak at l_pos().  mark(kend, c) records a knot inside the
-    // piece (kend in [b0, b1 - 1)) once the bracket is resolved.
+    // Advance L when go (= steps_l() at the start of the iteration); vk, ak
+    // at L.k.  mark(kend, c, on) records a knot inside the piece (kend in
+    // [b0, b1 - 1)) once the bracket is resolved.
     template <class Mark>
-    __host__ __device__ inline void step_l(float vk, float ak, const Mark& mark)
+    __host__ __device__ inline void step_l(bool go, float vk, float ak, const Mark& mark)
     {
-        if (!steps_l()) return;
+        if (!go) return;
         int kend;
         float c;
         const bool fin = lean_step(L, m, vk, ak, kend, c);
         const bool br = bracket;
-        lastL = fin && br ? kend : lastL;
-        ancL = fin && br ? L.nA : ancL;
-        const bool out = fin && !br;
-        mark(kend, c, out && kend >= b0 && kend < b1 - 1);
-        const bool covers = out && kend >= b1 - 1;
+        lastL = fin & br ? kend : lastL;
+        ancL = fin & br ? L.nA : ancL;
+        const bool out = fin & !br;
+        mark(kend, c, out & (kend >= b0) & (kend < b1 - 1));
+        const bool covers = out & (kend >= b1 - 1);
         c_last = covers ? c : c_last;
-        scanning = scanning && !covers;
+        scanning = scanning & !covers;
     }
 
     // Advance L once no lane brackets any more (every lane is exact from its
@@ -208,10 +208,10 @@ struct LeanLane {
         scanning = !covers;
     }
 
-    // advance U; vk, ak at u_pos()
-    __host__ __device__ inline void step_u(float vk, float ak)
+    // advance U when go (= needs_u() at the start of the iteration); vk, ak at U.k
+    __host__ __device__ inline void step_u(bool go, float vk, float ak)
     {
-        if (!needs_u()) return;
+        if (!go) return;
         int kend;
         float c;
         const bool fin = lean_step(U, m, vk, ak, kend, c);
@@ -228,7 +228,7 @@ struct LeanLane {
             bracket = false;  // merged at a knot before the piece: L is exact from here
             U.on = false;
         } else if ((lastL >= b0 - 1 && lastU >= b0 - 1) || !L.on || !U.on) {
-            W *= 4;  // no shared knot before the piece: start further back
+            W *= 2;  // no shared knot before the piece: start further back
             restart(a_before);
         }
     }

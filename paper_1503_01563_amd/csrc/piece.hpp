@@ -154,10 +154,12 @@ struct PieceLane {
     __device__ __forceinline__ bool needs_u() const { return scanning && bracket && lastU <= lastL; }
 
 
-    // advance U; rv = values at u_pos() (read before step_l)
-    __device__ __forceinline__ void step_u(const RingVals<NR>& rv)
+    // advance U when go (= needs_u() before step_l ran: deciding after L's
+    // step would let U pass a knot that L has just reached, so the shared
+    // knot would be missed and the lane restart); rv = values at u_pos()
+    __device__ __forceinline__ void step_u(bool go, const RingVals<NR>& rv)
     {
-        if (!needs_u()) return;
+        if (!go) return;
         const int k = U.k;
         Seg<false> sg;
         const bool fin = scan_step<false>(U, m, rv.r[0], k + 1 < m ? rv.r[1] : 0.f, sg);

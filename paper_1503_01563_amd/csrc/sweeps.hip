@@ -236,14 +236,19 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     const int lo = base;
     int hi = b1 + cfg.tail < m ? b1 + cfg.tail : m;
     const int slots = cfg.reach_lo + cfg.len + cfg.reach_hi;
-    // one extra row per array takes the writes of lanes with nothing to emit
+    // two spare rows per array: writes of lanes with nothing to emit, and
+    // values fetched from outside the window (row slots for L, slots + 1 for U)
     float* lv = lds;                       // [slot][lane]: v, later segment value
-    float* la = lds + (slots + 1) * kPad;  // [slot][lane]: a, later edge dual
+    float* la = lds + (slots + 2) * kPad;  // [slot][lane]: a, later edge dual
 
     // Stage positions [qa, qb) of the 64 chains: B independent loads per lane
     // in flight before any LDS write (more for the initial window, when the
     // scan state is not live yet, 8 for growth inside the solve loop).  Rows are walked (row, position)
     // flattened over the lanes, so consecutive lanes read consecutive positions.
+    // The loads are unconditional (elements past the end re-read a valid one)
+    // so that they are all issued before the first wait; only the LDS writes
+    // are predicated.  Weights are staged as a + 0: a -0 weight must not look
+    // like a knot mark of the value sweeps.
     constexpr int kBatch = 16;
     auto stage = [&](int qa, int qb, auto batch) {
         constexpr int B = decltype(batch)::value;
@@ -258,11 +263,9 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
                 int r2 = rr, q2 = q;
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
-                    if (rr < nrows) {
-                        const int i = (c0 + rr) * g.W + qa + q;
-                        vv[u] = mode.v_at(i);
-                        aa[u] = mode.a_at(i) + 0.f;
-                    }
+                    const int i = (c0 + (rr < nrows ? rr : nrows - 1)) * g.W + qa + q;
+                    vv[u] = mode.v_at(i);
+                    aa[u] = mode.a_at(i);
                     rr += drr;
                     q += dq;
                     if (q >= len_r) {
@@ -275,7 +278,7 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
                     if (r2 < nrows) {
                         const int sl = (qa + q2 - base) * kPad + r2;
                         lv[sl] = vv[u];
-                        la[sl] = aa[u];
+                        la[sl] = aa[u] + 0.f;
                     }
                     r2 += drr;
                     q2 += dq;
@@ -290,19 +293,17 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
                 float vv[B], aa[B];
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
-                    const int q = qb0 + u;
-                    if (q < qb) {
-                        const int i = ch.base + q * ch.stride;
-                        vv[u] = mode.v_at(i);
-                        aa[u] = mode.a_at(i) + 0.f;
-                    }
+                    const int q = qb0 + u < qb ? qb0 + u : qb - 1;
+                    const int i = ch.base + q * ch.stride;
+                    vv[u] = mode.v_at(i);
+                    aa[u] = mode.a_at(i);
                 }
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
                     const int q = qb0 + u;
                     if (q < qb) {
                         lv[(q - base) * kPad + lane] = vv[u];
-                        la[(q - base) * kPad + lane] = aa[u];
+                        la[(q - base) * kPad + lane] = aa[u] + 0.f;
                     }
                 }
             }
@@ -371,16 +372,34 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
             }
             return in ? (q - base) * kPad + lane : spare;
         };
-        // while some lane brackets: both scans, U only where it brackets
+        // While some lane brackets: both scans, U only where it brackets.
+        // Positions outside the window go through the spare rows (L's in
+        // row `slots`, U's in row `slots + 1`), one check for both.
+        auto in_window = [&](int q) { return (q >= lo) & (q < hi); };
+        const int spare_u = spare + kPad;
         while (__any(pl.bracket && pl.scanning)) {
             grow();
-            const int ql = pl.l_pos(lo), qu = pl.u_pos(lo);
-            const int sl = slot_of(ql);
-            const float vl = lv[sl], al = la[sl];
-            const int su = slot_of(qu);
-            const float vu = lv[su], au = la[su];
-            pl.step_l(vl, ql + 1 < m ? al : 0.f, mark);
-            pl.step_u(vu, qu + 1 < m ? au : 0.f);
+            const bool gl = pl.steps_l(), gu = pl.needs_u();
+            const int ql = gl ? pl.L.k : lo, qu = gu ? pl.U.k : lo;
+            const bool inl = in_window(ql), inu = in_window(qu);
+            if (__any(!inl || !inu)) {
+                if (!inl) {
+                    const int i = ch.base + ql * ch.stride;
+                    lv[spare] = mode.v_at(i);
+                    la[spare] = mode.a_at(i);
+                }
+                if (!inu) {
+                    const int i = ch.base + qu * ch.stride;
+                    lv[spare_u] = mode.v_at(i);
+                    la[spare_u] = mode.a_at(i);
+                }
+                wave_fence();
+            }
+            const int sl = inl ? (ql - base) * kPad + lane : spare;
+            const int su = inu ? (qu - base) * kPad + lane : spare_u;
+            const float vl = lv[sl], al = la[sl], vu = lv[su], au = la[su];
+            pl.step_l(gl, vl, ql + 1 < m ? al : 0.f, mark);
+            pl.step_u(gu, vu, qu + 1 < m ? au : 0.f);
             pl.resolve(a_before);
         }
         // then L alone in every lane until its piece is covered
@@ -430,10 +449,11 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
             if (!inside(ql)) rl = glob_at(ql);
             if (!inside(qu)) ru = glob_at(qu);
         }
+        const bool gu = pl.needs_u();  // decided before L steps (see lean.hpp)
         pl.fill(rf, emit);
         pl.step_l(rl);
         if (__any(pl.bracket && pl.scanning)) {
-            pl.step_u(ru);
+            pl.step_u(gu, ru);
             pl.resolve(a_before);
         }
     }
@@ -718,7 +738,7 @@ inline int items_of(const Geo& g, int axis, const PieceCfg& cfg)
 
 inline size_t lds_bytes(const PieceCfg& cfg)
 {
-    return sizeof(float) * 2 * (size_t)(cfg.reach_lo + cfg.len + cfg.reach_hi + 1) * kPad;
+    return sizeof(float) * 2 * (size_t)(cfg.reach_lo + cfg.len + cfg.reach_hi + 2) * kPad;
 }
 
 // the launch of k_sweep_triple with the latency / throughput mode decided on
@@ -862,7 +882,7 @@ PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items)
     // short and LDS small (more waves resident).
     const long items = launch_items > 0 ? launch_items : (long)groups * cfg.pieces;
     const bool latency_bound = items <= kLatencyItems;
-    cfg.overlap = cut ? (latency_bound ? 24 : 8) : 0;
+    cfg.overlap = cut ? (latency_bound ? 12 : 8) : 0;
     cfg.tail = cut ? 8 : 0;
     // LDS: the overlap plus the weight of the edge in front of it, the piece,
     // and the tail -- plus one block of tail growth when latency bound (with
