@@ -146,13 +146,15 @@ struct Walk {
 // LB(y) = sum_i min(y_i + w_i, 0).  Both are formed in FP64 from the FP32
 // duals, which stay bounded by the weights, unlike the diverging state.
 // Returns the voxel's LB term and writes its primal.
+template <int ND>
 __device__ __forceinline__ double primal_voxel(const Geo& g, const float* __restrict__ w,
                                                const Ptr3& p, float* __restrict__ xc, int i, const Coords& c)
 {
     const int st[3] = {1, g.W, g.W * g.H};
     const int cc[3] = {c.x, c.y, c.d};
     double y = 0.0;
-    for (int j = 0; j < g.ndim; ++j) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
         y -= (double)p.p[j][i];  // zero on the last slice
         if (cc[j] > 0) y += (double)p.p[j][i - st[j]];
     }
@@ -161,12 +163,59 @@ __device__ __forceinline__ double primal_voxel(const Geo& g, const float* __rest
     return s < 0.0 ? s : 0.0;
 }
 
+// The walk in groups of kGroup voxels: the loads of a whole group are issued
+// before any of its stores (the arrays are not known not to alias, so a store
+// would otherwise hold back the next voxel's loads), then the voxels are
+// finished in walk order, so the sums are the same as voxel by voxel.
+constexpr int kGroup = 4;
+
+template <int ND>
 __global__ void __launch_bounds__(kReduceThreads)
 k_primal(Geo g, const float* __restrict__ w, Ptr3 p, float* __restrict__ xc,
          double* __restrict__ partials)
 {
+    const int st[3] = {1, g.W, g.W * g.H};
     double lb = 0.0;
-    for (Walk k(g); k.i < g.n; k.next(g)) lb += primal_voxel(g, w, p, xc, k.i, k.c);
+    Walk k(g);
+    while (k.i < g.n) {
+        int idx[kGroup];
+        bool ok[kGroup];
+        float pc[kGroup][ND], pb[kGroup][ND], wv[kGroup];
+        bool hb[kGroup][ND];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            ok[u] = k.i < g.n;
+            idx[u] = ok[u] ? k.i : 0;
+            const int cc[3] = {k.c.x, k.c.y, k.c.d};
+#pragma unroll
+            for (int j = 0; j < ND; ++j) hb[u][j] = ok[u] & (cc[j] > 0);
+            k.next(g);
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            const int i = idx[u];
+            wv[u] = w[i];
+#pragma unroll
+            for (int j = 0; j < ND; ++j) {
+                pc[u][j] = p.p[j][i];  // zero on the last slice
+                pb[u][j] = p.p[j][hb[u][j] ? i - st[j] : i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            double y = 0.0;
+#pragma unroll
+            for (int j = 0; j < ND; ++j) {
+                y -= (double)pc[u][j];
+                if (hb[u][j]) y += (double)pb[u][j];
+            }
+            const double sv = y + (double)wv[u];
+            if (ok[u]) {
+                xc[idx[u]] = (float)(-sv);
+                lb += sv < 0.0 ? sv : 0.0;
+            }
+        }
+    }
     double v[1] = {lb};
     block_reduce_store<1>(v, partials + blockIdx.x);
 }
@@ -216,6 +265,7 @@ struct Ladder {
     }
 };
 
+template <int ND>
 __device__ __forceinline__ void cut_voxel(const Geo& g, const float* __restrict__ xc,
                                           const float* __restrict__ w, const Ptr3& a,
                                           const Ptr3& p, const Taus& tz, int i, const Coords& c,
@@ -227,7 +277,8 @@ __device__ __forceinline__ void cut_voxel(const Geo& g, const float* __restrict_
     const float xi = xc[i];
     const int ci = ladder_count(xi, tz);
     L.node(ci, (double)w[i]);
-    for (int j = 0; j < g.ndim; ++j) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
         if (cc[j] + 1 < ext[j]) {
             const float xn = xc[i + st[j]];
             const double aj = (double)a.p[j][i];
@@ -238,12 +289,50 @@ __device__ __forceinline__ void cut_voxel(const Geo& g, const float* __restrict_
     }
 }
 
+template <int ND>
 __global__ void __launch_bounds__(kReduceThreads)
 k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, Ptr3 a, Ptr3 p,
              Taus tz, double* __restrict__ partials)
 {
+    const int st[3] = {1, g.W, g.W * g.H};
+    const int ext[3] = {g.W, g.H, g.D};
     Ladder L;
-    for (Walk k(g); k.i < g.n; k.next(g)) cut_voxel(g, xc, w, a, p, tz, k.i, k.c, L);
+    Walk k(g);
+    while (k.i < g.n) {
+        // loads of a group first (see kGroup), then the voxels in walk order
+        bool ok[kGroup], he[kGroup][ND];
+        float xi[kGroup], wv[kGroup], xn[kGroup][ND], av[kGroup][ND], pv[kGroup][ND];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            ok[u] = k.i < g.n;
+            const int i = ok[u] ? k.i : 0;
+            const int cc[3] = {k.c.x, k.c.y, k.c.d};
+            xi[u] = xc[i];
+            wv[u] = w[i];
+#pragma unroll
+            for (int j = 0; j < ND; ++j) {
+                he[u][j] = cc[j] + 1 < ext[j];
+                xn[u][j] = xc[he[u][j] ? i + st[j] : i];
+                av[u][j] = a.p[j][i];
+                pv[u][j] = p.p[j][i];
+            }
+            k.next(g);
+        }
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) {
+            if (!ok[u]) continue;
+            const int ci = ladder_count(xi[u], tz);
+            L.node(ci, (double)wv[u]);
+#pragma unroll
+            for (int j = 0; j < ND; ++j) {
+                if (!he[u][j]) continue;  // no edge beyond the last slice
+                const double aj = (double)av[u][j];
+                L.edge(ci, ladder_count(xn[u][j], tz), aj);
+                const double dx = (double)xn[u][j] - (double)xi[u];
+                L.e[kNumTau] += aj * fabs(dx) - (double)pv[u][j] * dx;
+            }
+        }
+    }
     block_reduce_store<kNumTau + 1>(L.e, partials + (size_t)blockIdx.x * (kNumTau + 1));
 }
 
@@ -379,7 +468,7 @@ k_batch_primal(BatchLaunch b, double* __restrict__ partials)
     double lb = 0.0;
     for (Walk k(t.g, ((int)blockIdx.x - t.blk0) * kReduceThreads + threadIdx.x, t.nblk * kReduceThreads); k.i < t.g.n;
          k.next(t.g))
-        lb += primal_voxel(t.g, t.w, p, t.xc, k.i, k.c);
+        lb += primal_voxel<2>(t.g, t.w, p, t.xc, k.i, k.c);
     double v[1] = {lb};
     block_reduce_store<1>(v, partials + (size_t)blockIdx.x * kCertValues + kNumTau + 1);
 }
@@ -397,7 +486,7 @@ k_batch_cut(BatchLaunch b, Taus tz, double* __restrict__ partials)
     Ladder L;
     for (Walk k(t.g, ((int)blockIdx.x - t.blk0) * kReduceThreads + threadIdx.x, t.nblk * kReduceThreads); k.i < t.g.n;
          k.next(t.g))
-        cut_voxel(t.g, t.xc, t.w, a, p, tz, k.i, k.c, L);
+        cut_voxel<2>(t.g, t.xc, t.w, a, p, tz, k.i, k.c, L);
     block_reduce_store<kNumTau + 1>(L.e, partials + (size_t)blockIdx.x * kCertValues);
 }
 
@@ -592,9 +681,13 @@ hipError_t launch_cert(const Geo& g, const float* w, const float* const* a,
     const int nb = reduce_blocks(g.n);
     double* part_lb = partials;
     double* part_cut = partials + kReduceBlocks;
-    hipLaunchKernelGGL(k_primal, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pp, xc, part_lb);
-    hipLaunchKernelGGL(k_cut_ladder, dim3(nb), dim3(kReduceThreads), 0, s, g, xc, w, pa, pp, tz,
-                       part_cut);
+    if (g.ndim == 3) {
+        hipLaunchKernelGGL(k_primal<3>, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pp, xc, part_lb);
+        hipLaunchKernelGGL(k_cut_ladder<3>, dim3(nb), dim3(kReduceThreads), 0, s, g, xc, w, pa, pp, tz, part_cut);
+    } else {
+        hipLaunchKernelGGL(k_primal<2>, dim3(nb), dim3(kReduceThreads), 0, s, g, w, pp, xc, part_lb);
+        hipLaunchKernelGGL(k_cut_ladder<2>, dim3(nb), dim3(kReduceThreads), 0, s, g, xc, w, pa, pp, tz, part_cut);
+    }
     hipLaunchKernelGGL(k_finalize_cert, dim3(1), dim3(kReduceThreads), 0, s, part_cut, part_lb, nb, out);
     return hipGetLastError();
 }

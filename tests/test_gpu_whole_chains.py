@@ -57,6 +57,28 @@ def test_long_chains_match_reference(dev, shape, iters):
     assert np.abs(x - ref["x"]).max() / scale <= REL_TOL
 
 
+@pytest.mark.parametrize("shape,variant", [((16320, 4), 1), ((16321, 4), 1), ((16384, 4), 1),
+                                           ((4, 128, 130), 2), ((4, 120, 136), 2)])
+@pytest.mark.parametrize("iters", [2, 7])
+def test_many_chains_take_the_global_sweep(dev, shape, variant, iters):
+    """Families of 16321 chains or more (256 or more 64-chain waves) take the
+    global-memory whole-chain sweep over many blocks, fewer the LDS one: the
+    2D boundary 16320 / 16321 rows, 16384 rows, and volumes whose depth
+    family has 16640 (global) and 16320 (LDS) chains, in the product space;
+    iterates against the reference, then the exact cut against max-flow."""
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid(shape, 970 + iters)
+    wt, at = T(w, dev), [T(x, dev) for x in a]
+    res = mc.tv_solve(wt, at, max_iters=iters, gap_tol=0.0, variant=variant, whole_chains=True)
+    ref = oracle.dr_solve(w, a, variant=variant - 1, max_iters=iters, gap_tol=0.0)
+    x = res.x.cpu().numpy()
+    scale = max(1.0, np.abs(ref["x"]).max())
+    assert np.abs(x - ref["x"]).max() / scale <= REL_TOL
+    if iters == 7:
+        res = mc.tv_solve(wt, at, max_iters=3000, check_every=2, variant=variant, whole_chains=True)
+        assert res.converged and res.energy == oracle.mincut(w, a, "dinic")[0]
+
+
 @pytest.mark.parametrize("seed", range(1000, 1006))
 def test_exact_against_maxflow(dev, seed):
     from paper_1503_01563_amd import mc
