@@ -315,147 +315,91 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     using Small = std::integral_constant<int, 8>;
     stage(lo, hi, Big{});
 
-    // solve.  Values are read from LDS at an index clamped into the window;
-    // only when some lane needs a position outside it (beyond the reserve) does
-    // the wave take a separate path that reads those from global memory.
-    // Keeping the two paths apart keeps the common reads plain LDS loads.
-    auto lds_at = [&](int q) -> RingVals<2> {
-        const int qc = q < lo ? lo : (q >= hi ? hi - 1 : q);
-        const int sl = (qc - base) * kPad + lane;
-        return {{lv[sl], la[sl]}};
-    };
-    auto glob_at = [&](int q) -> RingVals<2> {
-        const int i = ch.base + q * ch.stride;
-        return {{mode.v_at(i), mode.a_at(i)}};
-    };
-    auto inside = [&](int q) { return q >= lo && q < hi; };
+    // solve: the lean scan of each lane (see lean.hpp).  Knots inside the
+    // piece are recorded in LDS at their slot: value sweeps store the segment
+    // value and a negative weight as the mark; sweeps with duals store the
+    // FP64 segment value as a float pair (the knot's v and a are read again
+    // from global memory by the backward pass) and mark the knot in the
+    // lane's bit masks.
     auto a_before = [&](int q) -> float {
         return (q >= lo && q < hi) ? la[(q - base) * kPad + lane] : mode.a_at(ch.base + q * ch.stride);
     };
-    auto emit = [&](int q, auto cv, auto pr, bool last, bool on) {
-        const int sl = (on ? q - base : slots) * kPad + lane;
-        lv[sl] = (float)cv;
-        if constexpr (kExact) la[sl] = last ? 0.f : clip_dual(pr, la[sl]);
-    };
     constexpr int kGrow = 8;
     const int W0 = cfg.overlap > 0 ? cfg.overlap : 1;
-    if constexpr (!kExact) {
-        // values only: the lean scan marks knots in LDS, a backward pass fills
-        LeanLane pl;
-        pl.begin(valid, m, b0, b1, W0, a_before);
-        auto mark = [&](int q, float cv, bool on) {
-            const int sl = (on ? q - base : slots) * kPad + lane;
+    LeanLaneT<kExact> pl;
+    pl.begin(valid, m, b0, b1, W0, a_before);
+    auto mark = [&](int q, float cv, const LeanSeg& sg, bool on) {
+        const int sl = (on ? q - base : slots) * kPad + lane;
+        if constexpr (kExact) {
+            const float chi = (float)sg.c;
+            lv[sl] = chi;
+            la[sl] = (float)(sg.c - (double)chi);
+        } else {
             lv[sl] = cv;
             la[sl] = -1.f;
-        };
-        auto grow = [&]() {
-            if (hi < hi_cap && __any(pl.scanning && pl.L.k >= hi)) {
-                const int nh = hi + kGrow < hi_cap ? hi + kGrow : hi_cap;
-                stage(hi, nh, Small{});
-                hi = nh;
-            }
-        };
-        // Slot of position q for a scan read.  A position outside the window
-        // (rare: the deeper overlap after a failed bracket, a tail beyond the
-        // reserve) is fetched from global memory into the lane's slot of the
-        // spare row first, so that the read itself is always an LDS read.
-        const int spare = slots * kPad + lane;
-        auto slot_of = [&](int q) {
-            const bool in = (q >= lo) & (q < hi);
-            if (__any(!in)) {
-                if (!in) {
-                    const int i = ch.base + q * ch.stride;
-                    lv[spare] = mode.v_at(i);
-                    la[spare] = mode.a_at(i);
-                }
-                wave_fence();
-            }
-            return in ? (q - base) * kPad + lane : spare;
-        };
-        // While some lane brackets: both scans, U only where it brackets.
-        // Positions outside the window go through the spare rows (L's in
-        // row `slots`, U's in row `slots + 1`), one check for both.
-        auto in_window = [&](int q) { return (q >= lo) & (q < hi); };
-        const int spare_u = spare + kPad;
-        while (__any(pl.bracket && pl.scanning)) {
-            grow();
-            const bool gl = pl.steps_l(), gu = pl.needs_u();
-            const int ql = gl ? pl.L.k : lo, qu = gu ? pl.U.k : lo;
-            const bool inl = in_window(ql), inu = in_window(qu);
-            if (__any(!inl || !inu)) {
-                if (!inl) {
-                    const int i = ch.base + ql * ch.stride;
-                    lv[spare] = mode.v_at(i);
-                    la[spare] = mode.a_at(i);
-                }
-                if (!inu) {
-                    const int i = ch.base + qu * ch.stride;
-                    lv[spare_u] = mode.v_at(i);
-                    la[spare_u] = mode.a_at(i);
-                }
-                wave_fence();
-            }
-            const int sl = inl ? (ql - base) * kPad + lane : spare;
-            const int su = inu ? (qu - base) * kPad + lane : spare_u;
-            const float vl = lv[sl], al = la[sl], vu = lv[su], au = la[su];
-            pl.step_l(gl, vl, ql + 1 < m ? al : 0.f, mark);
-            pl.step_u(gu, vu, qu + 1 < m ? au : 0.f);
-            pl.resolve(a_before);
         }
-        // then L alone in every lane until its piece is covered
-        while (__any(pl.scanning)) {
-            grow();
-            const int ql = pl.scanning ? pl.L.k : lo;
-            const int sl = slot_of(ql);
-            const float vl = lv[sl], al = la[sl];
-            if (pl.scanning) pl.step_plain(vl, ql + 1 < m ? al : 0.f, mark);
-        }
-        wave_fence();
-        if (g.restarts) {
-            const int nr = __popcll(__ballot(valid && pl.W != W0));
-            const int nv = __popcll(__ballot(valid));
-            if (lane == 0) {
-                atomicAdd(g.restarts, nr);
-                atomicAdd(g.restarts + 1, nv);
-            }
-        }
-        // every position takes the value of the first knot at or after it;
-        // the segment covering b1 - 1 is in registers
-        float cur = pl.c_last;
-        for (int q = b1 - 1; q >= b0; --q) {
-            const int sl = (q - base) * kPad + lane;
-            const float aq = la[sl], vq = lv[sl];
-            cur = aq < 0.f ? vq : cur;
-            lv[sl] = cur;
-        }
-        wave_fence();
-    } else {
-    PieceLane<2, kExact> pl;
-    pl.begin(valid, m, b0, b1, W0, a_before);
-    while (__any(pl.busy())) {
-        // some lane's scan is about to read past the window: stage the next block
+    };
+    auto grow = [&]() {
         if (hi < hi_cap && __any(pl.scanning && pl.L.k >= hi)) {
             const int nh = hi + kGrow < hi_cap ? hi + kGrow : hi_cap;
             stage(hi, nh, Small{});
             hi = nh;
         }
-        // the three reads of this iteration, issued together
-        const int qf = pl.fill_pos(lo), ql = pl.l_pos(lo), qu = pl.u_pos(lo);
-        // (after a restart the scans, and the fill that carries the duals
-        // forward from their merge knot, can start in front of the window)
-        RingVals<2> rf = lds_at(qf), rl = lds_at(ql), ru = lds_at(qu);
-        if (__any(!inside(qf) || !inside(ql) || !inside(qu))) {
-            if (!inside(qf)) rf = glob_at(qf);
-            if (!inside(ql)) rl = glob_at(ql);
-            if (!inside(qu)) ru = glob_at(qu);
+    };
+    // Slot of position q for a scan read.  A position outside the window
+    // (rare: the deeper overlap after a failed bracket, a tail beyond the
+    // reserve) is fetched from global memory into the lane's slot of the
+    // spare row first, so that the read itself is always an LDS read.
+    const int spare = slots * kPad + lane;
+    auto slot_of = [&](int q) {
+        const bool in = (q >= lo) & (q < hi);
+        if (__any(!in)) {
+            if (!in) {
+                const int i = ch.base + q * ch.stride;
+                lv[spare] = mode.v_at(i);
+                la[spare] = mode.a_at(i);
+            }
+            wave_fence();
         }
-        const bool gu = pl.needs_u();  // decided before L steps (see lean.hpp)
-        pl.fill(rf, emit);
-        pl.step_l(rl);
-        if (__any(pl.bracket && pl.scanning)) {
-            pl.step_u(gu, ru);
-            pl.resolve(a_before);
+        return in ? (q - base) * kPad + lane : spare;
+    };
+    // While some lane brackets: both scans, U only where it brackets.
+    // Positions outside the window go through the spare rows (L's in
+    // row `slots`, U's in row `slots + 1`), one check for both.
+    auto in_window = [&](int q) { return (q >= lo) & (q < hi); };
+    const int spare_u = spare + kPad;
+    while (__any(pl.bracket && pl.scanning)) {
+        grow();
+        const bool gl = pl.steps_l(), gu = pl.needs_u();
+        const int ql = gl ? pl.L.k : lo, qu = gu ? pl.U.k : lo;
+        const bool inl = in_window(ql), inu = in_window(qu);
+        if (__any(!inl || !inu)) {
+            if (!inl) {
+                const int i = ch.base + ql * ch.stride;
+                lv[spare] = mode.v_at(i);
+                la[spare] = mode.a_at(i);
+            }
+            if (!inu) {
+                const int i = ch.base + qu * ch.stride;
+                lv[spare_u] = mode.v_at(i);
+                la[spare_u] = mode.a_at(i);
+            }
+            wave_fence();
         }
+        const int sl = inl ? (ql - base) * kPad + lane : spare;
+        const int su = inu ? (qu - base) * kPad + lane : spare_u;
+        const float vl = lv[sl], al = la[sl], vu = lv[su], au = la[su];
+        pl.step_l(gl, vl, ql + 1 < m ? al : 0.f, mark);
+        pl.step_u(gu, vu, qu + 1 < m ? au : 0.f);
+        pl.resolve(a_before);
+    }
+    // then L alone in every lane until its piece is covered
+    while (__any(pl.scanning)) {
+        grow();
+        const int ql = pl.scanning ? pl.L.k : lo;
+        const int sl = slot_of(ql);
+        const float vl = lv[sl], al = la[sl];
+        if (pl.scanning) pl.step_plain(vl, ql + 1 < m ? al : 0.f, mark);
     }
     wave_fence();
     if (g.restarts) {
@@ -468,7 +412,56 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
             atomicAdd(g.restarts + 1, nv);
         }
     }
+    if constexpr (!kExact) {
+        // every position takes the value of the first knot at or after it;
+        // the segment covering b1 - 1 is in registers
+        float cur = pl.c_last;
+        for (int q = b1 - 1; q >= b0; --q) {
+            const int sl = (q - base) * kPad + lane;
+            const float aq = la[sl], vq = lv[sl];
+            cur = aq < 0.f ? vq : cur;
+            lv[sl] = cur;
+        }
+    } else if (valid) {
+        // Backward from b1 - 1, where the covering segment's value and the
+        // dual of edge b1 - 1 are in registers: at a knot the value becomes
+        // the knot's segment value and the dual its exact +-a; inside a
+        // segment P_{q-1} = P_q + v_q - c, in FP64.  v and a of the knots
+        // come from global memory, 8 positions' loads issued together.
+        constexpr int kB = 8;
+        double cur = pl.c_last64, p = pl.p_b1;
+        for (int qt = b1 - 1; qt >= b0; qt -= kB) {
+            float gv[kB], ga[kB];
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int q = qt - u;
+                const bool kn = q >= b0 && ((pl.kmask >> (q - b0)) & 1ull);
+                gv[u] = ga[u] = 0.f;
+                if (kn) {
+                    const int i = ch.base + q * ch.stride;
+                    gv[u] = mode.v_at(i);
+                    ga[u] = mode.a_at(i);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kB; ++u) {
+                const int q = qt - u;
+                if (q >= b0) {
+                    const int sl = (q - base) * kPad + lane;
+                    const float x0 = lv[sl], x1 = la[sl];
+                    const bool kn = (pl.kmask >> (q - b0)) & 1ull;
+                    const bool up = (pl.umask >> (q - b0)) & 1ull;
+                    const float vq = kn ? gv[u] : x0, aq = kn ? ga[u] : x1;
+                    cur = kn ? (double)x0 + (double)x1 : cur;
+                    p = kn ? (double)(up ? aq : -aq) : p;
+                    lv[sl] = (float)cur;
+                    la[sl] = q == m - 1 ? 0.f : clip_dual(p, aq);
+                    p += (double)vq - cur;
+                }
+            }
+        }
     }
+    wave_fence();
 
     // store
     if (kRows) {
