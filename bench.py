@@ -83,7 +83,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-full", action="store_true",
                     help="also run the all-core oracle to its certificate on the volume (minutes)")
-    ap.add_argument("--warm-grids", type=int, default=16,
+    ap.add_argument("--warm-grids", type=int, default=64,
                     help="held-out 512x512 grids for the cold vs warm-start comparison (0: skip)")
     ap.add_argument("--no-image", dest="image", action="store_false",
                     help="skip the 1024x1024 image section")

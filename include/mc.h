@@ -233,17 +233,22 @@ int mc_cut_energy(mc_ctx *ctx, const mc_grid *grid, const float *w,
  *   a[2g], a[2g+1] [n_g] weights along W and along H (device).
  *   labels[g]      [n_g] uint8 output (device).
  *   x_out          nullable host array; x_out[g] nullable [n_g] primal estimate.
+ *   z_out          nullable host array; z_out[g] nullable [n_g] splitting state
+ *                  after the grid's last check (device).
  *   stats[g]       host; ms is the device time from the start of the solve to
- *                  the check that certified the grid (per-grid solve time).
+ *                  the check that certified the grid (per-grid solve time);
+ *                  iters the iteration of that check.
  * opts.check_every is rounded up to an even number of iterations: one check
- * period is captured in a hipGraph and replayed.  opts.batch_items > 0 fixes
- * the work items per sweep launch; 0 uses the value tuned on the first solve
- * of this batch shape.  Synchronises the stream.  Returns MC_OK when every
- * grid is certified, MC_NOT_CONVERGED otherwise.
+ * period is captured in a hipGraph and replayed; the iterations left below a
+ * whole period at opts.max_iters run outside the graph, so no grid runs more
+ * than opts.max_iters and every grid ends on a check.  opts.batch_items > 0
+ * fixes the work items per sweep launch; 0 uses the value tuned on the first
+ * solve of this batch shape.  Synchronises the stream.  Returns MC_OK when
+ * every grid is certified, MC_NOT_CONVERGED otherwise.
  */
 int mc_tv_solve_batched(mc_ctx *ctx, int n_grids, const mc_grid *grids,
                         const float *const *w, const float *const *a,
-                        uint8_t *const *labels, float *const *x_out, mc_stats *stats,
+                        uint8_t *const *labels, float *const *x_out, float *const *z_out, mc_stats *stats,
                         const mc_opts *opts, void *stream);
 
 /*

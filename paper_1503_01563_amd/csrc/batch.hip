@@ -156,8 +156,8 @@ unsigned long long signature(const std::vector<Geo>& geos)
 
 extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
                                    const float* const* w, const float* const* a,
-                                   uint8_t* const* labels, float* const* x_out, mc_stats* stats,
-                                   const mc_opts* opts_in, void* stream)
+                                   uint8_t* const* labels, float* const* x_out, float* const* z_out,
+                                   mc_stats* stats, const mc_opts* opts_in, void* stream)
 {
     if (!c) return set_error(MC_ERR_INVALID_ARG, "ctx is null");
     MC_HIP(hipSetDevice(c->device));
@@ -168,6 +168,7 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
     if (o.max_iters < 1 || o.check_every < 1) return set_error(MC_ERR_INVALID_ARG, "max_iters and check_every must be >= 1");
     if (o.variant == MC_VARIANT_PRODUCT) return set_error(MC_ERR_INVALID_ARG, "batched solves use the two-set form");
     const int K = (o.check_every + 1) / 2 * 2;  // iterations per replay, even: the state parity repeats
+    // (the state after it iterations is z[it & 1]; iteration it + 1 reads it)
 
     std::vector<Geo> geos((size_t)n_grids);
     size_t n_total = 0, floats = 0;
@@ -263,8 +264,10 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
     BatchLaunch bl;
     double* partials = nullptr;
     int it = 0;  // iterations done
-    // the first iteration from z = 0 (row proxes 0), on the plan of the first
-    // candidate; it is not timed by the autotuner (it sweeps only the columns)
+    // The first iteration from z = 0 (row proxes 0), on the plan of the first
+    // candidate; it is not timed by the autotuner (it sweeps only the
+    // columns).  The iterations before the replays leave at least one for
+    // the last check.
     if (o.max_iters > 1) {
         plan_pieces(pl, geos, n_total, items > 0 ? items : kCandidates[0]);
         if ((rc = upload(c, pl, s, &bl, &partials))) return rc;
@@ -291,7 +294,7 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
             ++it;
         }
         items = best;
-        c->tuned_items[sig] = best;
+        if (best_ms < INFINITY) c->tuned_items[sig] = best;  // (no candidate timed: nothing learnt)
     } else {
         // as many iterations as the autotuner runs, so that every call checks
         // at the same iterations (and reports the same results) whether it
@@ -301,19 +304,19 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
             ++it;
         }
     }
-    if ((it & 1) && it < o.max_iters) {  // an even iteration count before the graph (its parity)
-        MC_HIP(launch_batch_iteration(bl, it & 1, false, s));
-        ++it;
-    }
     plan_pieces(pl, geos, n_total, items);
     if ((rc = upload(c, pl, s, &bl, &partials))) return rc;
+    // checks at multiples of K, as mc_tv_solve checks at multiples of check_every
+    for (; it % K != 0 && it + 1 < o.max_iters; ++it) MC_HIP(launch_batch_iteration(bl, it & 1, false, s));
 
-    // one check period as a graph: K iterations, the last with duals, then the certificate
+    // one check period as a graph: K iterations from the current state parity,
+    // the last with duals, then the certificate
+    const int p0 = it & 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     MC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     hipError_t cap = hipSuccess;
-    for (int j = 0; j < K && cap == hipSuccess; ++j) cap = launch_batch_iteration(bl, j & 1, j == K - 1, s);
+    for (int j = 0; j < K && cap == hipSuccess; ++j) cap = launch_batch_iteration(bl, (p0 + j) & 1, j == K - 1, s);
     if (cap == hipSuccess) cap = launch_batch_check(bl, o.tau0, o.gap_tol, iter_dev, partials, s);
     hipError_t endc = hipStreamEndCapture(s, &graph);
     if (cap != hipSuccess) return hip_error(cap, "batch graph capture");
@@ -323,27 +326,47 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
     std::vector<BatchGrid> host_tab((size_t)n_grids);
     bool all_done = false;
     int graph_err = MC_OK;
-    // at least one replay: every grid gets a certificate and a primal to label
-    for (bool first = true; first || (it < o.max_iters && !all_done); first = false) {
+    auto read_done = [&]() -> int {
+        if (hipMemcpyAsync(host_tab.data(), bl.tab, host_tab.size() * sizeof(BatchGrid), hipMemcpyDeviceToHost,
+                           s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return hip_error(hipGetLastError(), "batch status read");
+        all_done = true;
+        for (const BatchGrid& t : host_tab) all_done = all_done && t.done;
+        return MC_OK;
+    };
+    while (it + K <= o.max_iters && !all_done) {
         if (launch_set_int(iter_dev, it + K, s) != hipSuccess || hipGraphLaunch(exec, s) != hipSuccess) {
             graph_err = hip_error(hipGetLastError(), "batch graph replay");
             break;
         }
         it += K;
-        if (hipMemcpyAsync(host_tab.data(), bl.tab, host_tab.size() * sizeof(BatchGrid),
-                           hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            graph_err = hip_error(hipGetLastError(), "batch status read");
-            break;
-        }
-        all_done = true;
-        for (const BatchGrid& t : host_tab) all_done = all_done && t.done;
+        if ((graph_err = read_done())) break;
     }
     (void)hipGraphExecDestroy(exec);
     (void)hipGraphDestroy(graph);
     if (graph_err) return graph_err;
+    // the iterations left below a whole period, the last with duals, then the
+    // last check (every solve ends on a check: each grid gets a certificate
+    // and a primal to label)
+    if (!all_done && it < o.max_iters) {
+        for (; it < o.max_iters; ++it)
+            MC_HIP(launch_batch_iteration(bl, it & 1, it + 1 == o.max_iters, s, it == 0));
+        MC_HIP(launch_set_int(iter_dev, it, s));
+        MC_HIP(launch_batch_check(bl, o.tau0, o.gap_tol, iter_dev, partials, s));
+        if ((rc = read_done())) return rc;
+    }
 
     MC_HIP(launch_batch_labels(bl, o.tau0, s));
+    if (z_out) {
+        // each grid's state after its last check (a certified grid stops iterating)
+        for (int gi = 0; gi < n_grids; ++gi) {
+            if (!z_out[gi]) continue;
+            const BatchGrid& t = host_tab[gi];
+            MC_HIP(hipMemcpyAsync(z_out[gi], t.z[t.iters & 1], sizeof(float) * (size_t)t.g.n,
+                                  hipMemcpyDeviceToDevice, s));
+        }
+    }
     unsigned long long t0 = 0;
     MC_HIP(hipMemcpyAsync(host_tab.data(), bl.tab, host_tab.size() * sizeof(BatchGrid), hipMemcpyDeviceToHost, s));
     MC_HIP(hipMemcpyAsync(&t0, t0_dev, sizeof(t0), hipMemcpyDeviceToHost, s));

@@ -174,8 +174,8 @@ struct BatchLaunch {
 
 // One two-set iteration over every unfinished grid; parity selects the state
 // buffer read.  With duals, the row/column duals are written for the check.
-// cold: the first iteration from z = 0, whose row proxes are 0 (q1 is zeroed
-// instead of swept; no duals are written for the rows).
+// cold: the first iteration from z = 0, whose row proxes are 0 (q1, and the
+// row duals when asked for, are zeroed instead of swept).
 hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, hipStream_t s,
                                   bool cold = false);
 // Certificate of every unfinished grid: grids whose certificate is below

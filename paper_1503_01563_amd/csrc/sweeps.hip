@@ -825,11 +825,15 @@ __global__ void __launch_bounds__(kLanes) k_batch_cols(BatchLaunch b, int parity
     sweep_piece<ModeCols2, false, kExact>(t.g, 1, item - t.item0_c, m, t.cc, lds);
 }
 
-// cold start: the row prox of z = 0 is 0 for every grid (blockIdx.y = grid)
-__global__ void k_batch_zero_rows(BatchLaunch b)
+// cold start: the row prox of z = 0 is 0 for every grid, with zero duals
+// (blockIdx.y = grid)
+__global__ void k_batch_zero_rows(BatchLaunch b, int duals)
 {
     const BatchGrid& t = b.tab[blockIdx.y];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < t.g.n; i += gridDim.x * blockDim.x) t.q1[i] = 0.f;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < t.g.n; i += gridDim.x * blockDim.x) {
+        t.q1[i] = 0.f;
+        if (duals) t.p[i] = 0.f;
+    }
 }
 
 }  // namespace
@@ -837,9 +841,8 @@ __global__ void k_batch_zero_rows(BatchLaunch b)
 hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, hipStream_t s, bool cold)
 {
     if (cold)
-        hipLaunchKernelGGL(k_batch_zero_rows, dim3(64, b.n_grids), dim3(256), 0, s, b);
+        hipLaunchKernelGGL(k_batch_zero_rows, dim3(64, b.n_grids), dim3(256), 0, s, b, duals ? 1 : 0);
     if (duals) {
-        // (a cold iteration never asks for duals: the first check comes later)
         if (!cold) hipLaunchKernelGGL(k_batch_rows<true>, dim3(b.items_r), dim3(kLanes), b.lds_r, s, b, parity);
         hipLaunchKernelGGL(k_batch_cols<true>, dim3(b.items_c), dim3(kLanes), b.lds_c, s, b, parity);
     } else {

@@ -98,3 +98,25 @@ def test_batched_config_64_uneven_grids(dev):
         e_star, _, _ = oracle.mincut(w, a, "dinic")
         for ce, res in runs.items():
             assert res.energy[k] == e_star, (k, ce)
+
+
+@pytest.mark.parametrize("max_iters,check_every", [(1, 4), (2, 2), (7, 4), (12, 4)])
+def test_batched_stops_at_max_iters(dev, max_iters, check_every):
+    """No grid runs past max_iters (the iterations left below a whole replay
+    period run outside the graph), every grid ends on a check, and the state
+    equals the single-grid solver's after as many iterations."""
+    from paper_1503_01563_amd import mc
+    shapes = [(37, 53), (64, 20), (1, 30), (9, 9)]
+    ws, As, host = batch_inputs(shapes, 3100, dev)
+    res = mc.tv_solve_batched(ws, As, max_iters=max_iters, check_every=check_every, gap_tol=0.0,
+                              return_x=True, return_z=True)
+    assert res.iters == [max_iters] * len(shapes)
+    for k in range(len(shapes)):
+        single = mc.tv_solve(ws[k], As[k], max_iters=max_iters, check_every=max_iters, gap_tol=0.0,
+                             return_x=True, return_z=True)
+        assert single.iters == max_iters
+        z_b = res.z[k].cpu().numpy()
+        z_s = single.z.view(shapes[k]).cpu().numpy()
+        assert np.array_equal(z_b, z_s), (k, float(np.abs(z_b - z_s).max()))
+        assert np.allclose(res.x[k].cpu().numpy(), single.x.view(shapes[k]).cpu().numpy(), rtol=1e-6, atol=1e-6)
+        assert res.energy[k] == single.energy

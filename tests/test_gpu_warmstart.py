@@ -164,26 +164,31 @@ def test_training_reduces_loss(dev):
 
 
 def test_trained_warm_start_gain(dev):
-    """The shipped trained network on 16 held-out 512x512 integer grids: cold and
-    warm starts both reach the exact minimum cut (energy equal to max-flow),
-    and the warm start needs fewer iterations in total."""
+    """The shipped trained network on the 64 held-out 512x512 integer test
+    grids: cold and warm starts both reach the exact minimum cut (the same
+    certified energy; equal to max-flow on the first 8), the warm start needs
+    fewer iterations in total, and it is faster on the median grid (time to
+    the exact cut, network included; per grid the median of 3 runs)."""
     import oracle
     from paper_1503_01563_amd import warmstart
     params, c = warmstart.load_params(dev)
     cold_it = warm_it = 0
     cold_ms, warm_ms = [], []
-    for s in range(warmstart.TEST_SEED0, warmstart.TEST_SEED0 + 16):
+    for k, s in enumerate(range(warmstart.TEST_SEED0, warmstart.TEST_SEED0 + 64)):
         w, a = gen.config_warm(s)
-        e_star = oracle.mincut(w, a, "dinic")[0]
         tw, ta = T(w, dev), [T(a[0], dev), T(a[1], dev)]
-        cold = warmstart.timed_solve(tw, ta)
-        warm = warmstart.timed_solve(tw, ta, params, c)
-        assert cold.result.converged and warm.result.converged, s
-        assert cold.result.energy == e_star and warm.result.energy == e_star, s
-        cold_it += cold.result.iters
-        warm_it += warm.result.iters
-        cold_ms.append(cold.ms)
-        warm_ms.append(warm.ms)
+        cold = [warmstart.timed_solve(tw, ta) for _ in range(3)]
+        warm = [warmstart.timed_solve(tw, ta, params, c) for _ in range(3)]
+        assert cold[-1].result.converged and warm[-1].result.converged, s
+        assert cold[-1].result.energy == warm[-1].result.energy, s
+        if k < 8:
+            assert cold[-1].result.energy == oracle.mincut(w, a, "dinic")[0], s
+        cold_it += cold[-1].result.iters
+        warm_it += warm[-1].result.iters
+        cold_ms.append(np.median([r.ms for r in cold]))
+        warm_ms.append(np.median([r.ms for r in warm]))
     print("iterations cold %d warm %d; median ms cold %.2f warm %.2f"
           % (cold_it, warm_it, np.median(cold_ms), np.median(warm_ms)))
     assert warm_it < cold_it
+    # paired per grid: the median of warm / cold time below 1
+    assert np.median(np.array(warm_ms) / np.array(cold_ms)) < 1.0
