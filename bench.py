@@ -442,10 +442,18 @@ def mixed_outer_loop_section(seed=2000, repeats=3):
     return out
 
 
+BATCH_BYTES_PER_ITER = 32  # per voxel and two-set iteration: rows z, a -> q1; columns q1, z, w, a -> z'
+
+
 def batched_section(seed=4000, count=64, repeats=3):
     """64 uneven integer grids (H, W uniform in [128, 1024]) solved together by
     mc_tv_solve_batched: per-grid time to the exact cut (device time from the
-    start of the solve to the check that certified the grid)."""
+    start of the solve to the check that certified the grid), for the replayed
+    graph of per-phase launches and for one persistent launch per check
+    period.  roofline: the sweeps' algorithmic bytes (32 B per voxel and
+    iteration over each grid's iterations) over the whole solve's device time
+    -- a lower bound of the sweep kernels' rate, since the solve time also
+    holds the checks."""
     import numpy as np
     import torch
 
@@ -454,19 +462,43 @@ def batched_section(seed=4000, count=64, repeats=3):
     grids = gen.config_batch(seed, count)
     ws = [torch.from_numpy(w).to(dev) for w, _ in grids]
     As = [[torch.from_numpy(x).to(dev) for x in a] for _, a in grids]
+    sizes = [w.size for w, _ in grids]
     mc.tv_solve_batched(ws, As, max_iters=3000, check_every=8)  # tunes the work items for this shape
-    runs = [mc.tv_solve_batched(ws, As, max_iters=3000, check_every=8) for _ in range(repeats)]
-    r = runs[-1]
+
+    def design(persistent):
+        runs = [mc.tv_solve_batched(ws, As, max_iters=3000, check_every=8, persistent=persistent)
+                for _ in range(repeats)]
+        r = runs[-1]
+        total_ms = float(np.median([np.max(q.ms) for q in runs]))
+        algo = float(sum(it * n for it, n in zip(r.iters, sizes))) * BATCH_BYTES_PER_ITER
+        achieved = algo / (total_ms * 1e-3) / 1e9
+        return {
+            "p50_ms": float(np.median([np.percentile(q.ms, 50) for q in runs])),
+            "p99_ms": float(np.median([np.percentile(q.ms, 99) for q in runs])),
+            "max_ms": total_ms,
+            "max_iters": int(max(r.iters)),
+            "all_certified": all(q.converged for q in runs),
+            "energies": list(r.energy),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                         "kernel": "k_batch_rows + k_batch_cols (whole-solve rate)",
+                         "bytes_per_voxel_iteration": BATCH_BYTES_PER_ITER},
+        }
+
+    graph = design(False)
+    pers = design(True)
+    same = graph.pop("energies") == pers.pop("energies")
     return {
         "workload": "%d integer grids, H and W uniform in [128, 1024] (%d voxels), seed %d"
-                    % (count, sum(w.size for w, _ in grids), seed),
+                    % (count, sum(sizes), seed),
         "check_every": 8,
-        "p50_ms": float(np.median([np.percentile(q.ms, 50) for q in runs])),
-        "p99_ms": float(np.median([np.percentile(q.ms, 99) for q in runs])),
-        "max_ms": float(np.median([np.max(q.ms) for q in runs])),
-        "max_iters": int(max(r.iters)),
-        "items_per_sweep": int(r.items),
-        "all_certified": all(q.converged for q in runs),
+        "items_per_sweep": int(mc.tv_solve_batched(ws, As, max_iters=3000, check_every=8).items),
+        "graph_replay": graph,
+        "persistent": pers,
+        "same_energies": same,
+        "p50_ms": graph["p50_ms"],
+        "p99_ms": graph["p99_ms"],
+        "all_certified": graph["all_certified"] and pers["all_certified"],
     }
 
 

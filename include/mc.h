@@ -80,6 +80,11 @@ extern "C" {
                                     and sweep whole chains for the rest of the solve when they are 1 in
                                     10 or more (one extra stream synchronisation); 8-connected grids
                                     use pieces */
+#define MC_BATCH_PERSISTENT 32u  /* mc_tv_solve_batched: run each check period's iterations as one
+                                    cooperative persistent launch (resident waves share out the work
+                                    items of every unfinished grid, a device-wide barrier between the
+                                    row and column phases) instead of replaying a graph of per-phase
+                                    launches; same results, slower on the 64-grid batch */
 
 /* mc_opts.variant */
 #define MC_VARIANT_AUTO 0        /* two-set form for 2D, product space for 3D */
@@ -115,7 +120,8 @@ typedef struct {
     float tau0;           /* labels S_tau = {x > tau} for the ladder tau = tau0 * (1, 1e-1, 1e-2,
                              1e-3, 0, -1e-3, -1e-2, -1e-1, -1); the first of least energy
                              is returned (default 1e-3) */
-    uint32_t flags;       /* MC_VALIDATE | MC_PROFILE | MC_WARM_MOVES | MC_WHOLE_CHAINS | MC_PIECE_CHAINS */
+    uint32_t flags;       /* MC_VALIDATE | MC_PROFILE | MC_WARM_MOVES | MC_WHOLE_CHAINS | MC_PIECE_CHAINS |
+                             MC_BATCH_PERSISTENT */
     int32_t batch_items;  /* mc_tv_solve_batched: work items per sweep launch (0 = tuned) */
     int32_t bcd_iters;    /* MC_VARIANT_BCD_DR: block coordinate descent iterations (0 = 16) */
     int32_t reserved[2];  /* must be 0 */

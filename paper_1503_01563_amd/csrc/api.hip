@@ -677,6 +677,7 @@ int mc_ctx_destroy(mc_ctx* c)
     for (hipEvent_t e : c->prof_ev) (void)hipEventDestroy(e);
     (void)hipFree(c->bbuf);
     (void)hipFree(c->bmeta);
+    (void)hipFree(c->bctl);
     (void)hipFree(c->nbuf);
     (void)hipFree(c->g8buf);
     (void)hipFree(c->vbuf);

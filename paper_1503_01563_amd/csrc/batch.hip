@@ -8,7 +8,9 @@
 // a wall-clock stamp), after which its work items return at once.  One check
 // period (an even number of iterations, the last one writing duals, then the
 // certificate) is captured in a hipGraph and replayed; the host looks at the
-// done flags once per replay.
+// done flags once per replay.  With MC_BATCH_PERSISTENT a period's iterations
+// run instead as one cooperative launch of resident waves with device-wide
+// barriers between phases (same iterates; slower, kept as an option).
 //
 // The split of chains into pieces (work items per launch) is chosen on the
 // first solve of a batch shape: the first iterations run with each candidate
@@ -81,8 +83,8 @@ void plan_pieces(Plan& pl, const std::vector<Geo>& geos, size_t n_total, int wan
     }
 }
 
-// Device metadata: a fixed header (start stamp, iteration counter), then the
-// table, the item and block maps and the reduction partials of a plan.
+// Device metadata: a fixed header (start stamp at 0, iteration counter at 64),
+// then the table, the item and block maps and the reduction partials of a plan.
 constexpr size_t kHeader = 256;
 
 size_t plan_bytes(const Plan& pl, size_t* o_ir, size_t* o_ic, size_t* o_bk, size_t* o_pa)
@@ -309,20 +311,74 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
     // checks at multiples of K, as mc_tv_solve checks at multiples of check_every
     for (; it % K != 0 && it + 1 < o.max_iters; ++it) MC_HIP(launch_batch_iteration(bl, it & 1, false, s));
 
-    // one check period as a graph: K iterations from the current state parity,
-    // the last with duals, then the certificate
+    // One check period: K iterations from the current state parity, the last
+    // with duals, then the certificate -- a captured graph of per-phase
+    // launches, or (MC_BATCH_PERSISTENT) one persistent launch for the
+    // iterations and the certificate launches after it.
     const int p0 = it & 1;
+    const bool persistent = (o.flags & MC_BATCH_PERSISTENT) != 0;
+    int* ctl = c->bctl;
+    int blocks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    MC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    hipError_t cap = hipSuccess;
-    for (int j = 0; j < K && cap == hipSuccess; ++j) cap = launch_batch_iteration(bl, (p0 + j) & 1, j == K - 1, s);
-    if (cap == hipSuccess) cap = launch_batch_check(bl, o.tau0, o.gap_tol, iter_dev, partials, s);
-    hipError_t endc = hipStreamEndCapture(s, &graph);
-    if (cap != hipSuccess) return hip_error(cap, "batch graph capture");
-    if (endc != hipSuccess) return hip_error(endc, "hipStreamEndCapture");
-    MC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-
+    if (persistent) {
+        // The control words are shared by waves on every XCD: in fine-grained
+        // memory, whose atomics are coherent across the XCDs' L2 caches (the
+        // default coarse-grained memory is coherent across XCDs only at
+        // kernel boundaries).
+        if (!c->bctl) {
+            MC_HIP(hipStreamSynchronize(s));
+            if (hipExtMallocWithFlags((void**)&c->bctl, 64, hipDeviceMallocFinegrained) != hipSuccess) {
+                (void)hipGetLastError();
+                c->bctl = nullptr;
+                return set_error(MC_ERR_NOMEM, "persistent batch control allocation failed");
+            }
+        }
+        ctl = c->bctl;
+        const size_t lds = std::max(bl.lds_r, bl.lds_c);
+        const auto f = c->persist_blocks.find(lds);
+        blocks = f != c->persist_blocks.end() ? f->second : batch_persistent_blocks(lds);  // (verified below)
+        if (blocks < 1) return set_error(MC_ERR_DEVICE, "no resident workgroups for the persistent batch launch");
+    } else {
+        MC_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t cap = hipSuccess;
+        for (int j = 0; j < K && cap == hipSuccess; ++j)
+            cap = launch_batch_iteration(bl, (p0 + j) & 1, j == K - 1, s);
+        if (cap == hipSuccess) cap = launch_batch_check(bl, o.tau0, o.gap_tol, iter_dev, partials, s);
+        hipError_t endc = hipStreamEndCapture(s, &graph);
+        if (cap != hipSuccess) return hip_error(cap, "batch graph capture");
+        if (endc != hipSuccess) return hip_error(endc, "hipStreamEndCapture");
+        MC_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    }
+    int ctl_h[8] = {0};
+    const size_t lds_p = std::max(bl.lds_r, bl.lds_c);
+    auto period = [&]() -> hipError_t {
+        hipError_t e = launch_set_int(iter_dev, it + K, s);
+        if (e != hipSuccess) return e;
+        if (!persistent) return hipGraphLaunch(exec, s);
+        // The occupancy query can promise more resident workgroups than run
+        // at once; the kernel's first barrier finds out before any work.  The
+        // first launch with a workgroup count waits for its verdict, and a
+        // launch whose workgroups were not all resident is repeated with as
+        // many as were (the count that works is remembered).
+        for (;;) {
+            const auto f = c->persist_blocks.find(lds_p);
+            const bool verified = f != c->persist_blocks.end() && f->second == blocks;
+            if ((e = hipMemsetAsync(ctl, 0, 8 * sizeof(int), s)) != hipSuccess) return e;
+            if ((e = launch_batch_persistent(bl, ctl, p0, K, blocks, s)) != hipSuccess) return e;
+            if (verified) break;
+            if ((e = hipMemcpyAsync(ctl_h, ctl, sizeof(ctl_h), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+            if (ctl_h[4] && ctl_h[6] == -1 && ctl_h[5] >= 8 && ctl_h[5] < blocks) {
+                blocks = ctl_h[5] / 8 * 8;
+                continue;
+            }
+            if (!ctl_h[4]) c->persist_blocks[lds_p] = blocks;
+            break;
+        }
+        if ((e = launch_batch_check(bl, o.tau0, o.gap_tol, iter_dev, partials, s)) != hipSuccess) return e;
+        return hipMemcpyAsync(ctl_h, ctl, sizeof(ctl_h), hipMemcpyDeviceToHost, s);  // read by read_done
+    };
     std::vector<BatchGrid> host_tab((size_t)n_grids);
     bool all_done = false;
     int graph_err = MC_OK;
@@ -331,20 +387,25 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
                            s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return hip_error(hipGetLastError(), "batch status read");
+        if (ctl_h[4])
+            return set_error(MC_ERR_DEVICE, "persistent batch launch: a device-wide barrier timed out (" +
+                                                std::to_string(ctl_h[5]) + " of " + std::to_string(ctl_h[7]) +
+                                                " workgroups arrived, phase " + std::to_string(ctl_h[6]) + ")");
         all_done = true;
         for (const BatchGrid& t : host_tab) all_done = all_done && t.done;
         return MC_OK;
     };
     while (it + K <= o.max_iters && !all_done) {
-        if (launch_set_int(iter_dev, it + K, s) != hipSuccess || hipGraphLaunch(exec, s) != hipSuccess) {
-            graph_err = hip_error(hipGetLastError(), "batch graph replay");
+        const hipError_t e = period();
+        if (e != hipSuccess) {
+            graph_err = hip_error(e, persistent ? "persistent batch launch" : "batch graph replay");
             break;
         }
         it += K;
         if ((graph_err = read_done())) break;
     }
-    (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (graph_err) return graph_err;
     // the iterations left below a whole period, the last with duals, then the
     // last check (every solve ends on a check: each grid gets a certificate

@@ -33,6 +33,8 @@ struct mc_ctx {
     float* bbuf = nullptr;           // per-grid state buffers, packed
     size_t bmeta_cap = 0;            // bytes in bmeta
     char* bmeta = nullptr;           // table, maps, partials, counters
+    int* bctl = nullptr;             // persistent batch launch control words (fine-grained memory)
+    std::map<size_t, int> persist_blocks;  // LDS bytes -> workgroups found resident at once
     std::map<unsigned long long, int> tuned_items;  // batch signature -> work items per launch
 
     // 8-connected grids: prox outputs of the four families, straightened zig-zag chains

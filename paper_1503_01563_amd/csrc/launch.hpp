@@ -178,6 +178,16 @@ struct BatchLaunch {
 // row duals when asked for, are zeroed instead of swept).
 hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, hipStream_t s,
                                   bool cold = false);
+// K iterations (from state parity p0, the last with duals) over every
+// unfinished grid as one cooperative launch of `blocks` resident waves (a
+// multiple of 8) that share out each phase's work items and meet at a
+// device-wide barrier between phases.  ctl: 8 ints, zero before the launch; ctl[4] != 0 after it
+// means a barrier gave up (the results are then invalid; ctl[5..7]: arrivals
+// seen, phase, workgroups).  Phase -1 is a barrier before any work: when it
+// gives up, fewer workgroups than launched were resident (ctl[5] of them)
+// and the launch changed nothing.
+int batch_persistent_blocks(size_t lds);
+hipError_t launch_batch_persistent(const BatchLaunch& b, int* ctl, int p0, int K, int blocks, hipStream_t s);
 // Certificate of every unfinished grid: grids whose certificate is below
 // gap_tol are marked done at iteration *iter_dev.
 hipError_t launch_batch_check(const BatchLaunch& b, float tau0, double gap_tol, const int* iter_dev,

@@ -836,7 +836,138 @@ __global__ void k_batch_zero_rows(BatchLaunch b, int duals)
     }
 }
 
+// ---- batched iterations as one persistent launch ------------------------------------
+//
+// Resident waves (one per workgroup, co-resident by a cooperative launch) run
+// K two-set iterations over every unfinished grid: per phase (the row sweeps,
+// then the column sweeps, of one iteration) the waves take the phase's work
+// items in the order the hardware deals workgroups (wave b takes virtual
+// workgroups b, b + waves, ..., each mapped by xcd_item), then all waves meet
+// at a device-wide barrier before the next phase reads what this one wrote.
+// (Claiming items from a device counter instead balances uneven items
+// dynamically but serialises on the counter: slower on the 64-grid batch.)
+// ctl: the barrier's arrival count and generation, an error flag and what
+// the first wave that gave up saw.  The spin at a barrier is bounded: past
+// kSpinLimit polls the wave sets the flag and returns, and every wave that
+// sees the flag returns too, so the launch always ends.
+constexpr int kCtlArrive = 2, kCtlGen = 3, kCtlErr = 4, kCtlDiag = 5;
+constexpr long kSpinLimit = 1L << 22;
+constexpr long kStartSpinLimit = 1L << 16;
+
+// ctl lives in fine-grained memory and its atomics are system scope, so that
+// every XCD sees one copy (ordinary device memory is kept coherent across the
+// XCDs' L2 caches only at kernel boundaries)
+__device__ __forceinline__ int ctl_load(int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM); }
+__device__ __forceinline__ int ctl_add(int* p, int v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void ctl_store(int* p, int v)
+{
+    __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// all waves of the launch past phase `phase` (-1: the start); false on a
+// barrier failure
+__device__ bool batch_barrier(int* ctl, int phase, long spin_limit)
+{
+    __threadfence();  // this wave's results before the arrival
+    int ok = 1;
+    if (threadIdx.x == 0) {
+        const int g0 = ctl_load(ctl + kCtlGen);
+        if (ctl_add(ctl + kCtlArrive, 1) == (int)gridDim.x - 1) {
+            ctl_store(ctl + kCtlArrive, 0);
+            __threadfence();
+            ctl_add(ctl + kCtlGen, 1);
+        } else {
+            long spins = 0;
+            while (ctl_load(ctl + kCtlGen) == g0) {
+                if (ctl_load(ctl + kCtlErr) != 0 || ++spins > spin_limit) {
+                    if (ctl_add(ctl + kCtlErr, 1) == 0) {
+                        // the first wave to give up records where: arrivals, phase, waves
+                        ctl_store(ctl + kCtlDiag, ctl_load(ctl + kCtlArrive));
+                        ctl_store(ctl + kCtlDiag + 1, phase);
+                        ctl_store(ctl + kCtlDiag + 2, (int)gridDim.x);
+                    }
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+    }
+    ok = __shfl(ok, 0);
+    __threadfence();  // the other waves' results after the departure
+    return ok != 0;
+}
+
+__global__ void __launch_bounds__(kLanes) k_batch_persistent(BatchLaunch b, int* ctl, int p0, int K)
+{
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    // Every workgroup must be resident for the barriers to complete; a first
+    // barrier (phase -1, short spin) checks that before any work is done.  If
+    // it gives up, its arrival count is the number that were resident.
+    if (!batch_barrier(ctl, -1, kStartSpinLimit)) return;
+    for (int j = 0; j < K; ++j) {
+        const int parity = (p0 + j) & 1;
+        const bool duals = j == K - 1;
+        for (int fam = 0; fam < 2; ++fam) {
+            const int phase = 2 * j + fam;
+            const int n_items = fam ? b.items_c : b.items_r;
+            for (int v = blockIdx.x; v < n_items; v += gridDim.x) {
+                const int idx = xcd_item(v, n_items);
+                if (fam == 0) {
+                    const int gi = b.item_grid_r[idx];
+                    const BatchGrid& t = b.tab[gi];
+                    if (t.done) continue;
+                    if (duals) {
+                        ModeRows2 m{t.z[parity], t.ax, t.q1, t.p};
+                        sweep_piece<ModeRows2, true, true>(t.g, 0, idx - t.item0_r, m, t.cr, lds);
+                    } else {
+                        ModeRows2 m{t.z[parity], t.ax, t.q1, nullptr};
+                        sweep_piece<ModeRows2, true, false>(t.g, 0, idx - t.item0_r, m, t.cr, lds);
+                    }
+                } else {
+                    const int gi = b.item_grid_c[idx];
+                    const BatchGrid& t = b.tab[gi];
+                    if (t.done) continue;
+                    if (duals) {
+                        ModeCols2 m{t.q1, t.z[parity], t.z[parity ^ 1], t.w, t.ay, t.p + t.g.n};
+                        sweep_piece<ModeCols2, false, true>(t.g, 1, idx - t.item0_c, m, t.cc, lds);
+                    } else {
+                        ModeCols2 m{t.q1, t.z[parity], t.z[parity ^ 1], t.w, t.ay, nullptr};
+                        sweep_piece<ModeCols2, false, false>(t.g, 1, idx - t.item0_c, m, t.cc, lds);
+                    }
+                }
+                wave_fence();  // the next item's staging overwrites this one's LDS
+            }
+            if (!batch_barrier(ctl, phase, kSpinLimit)) return;
+        }
+    }
+}
+
 }  // namespace
+
+// Workgroups of k_batch_persistent that are resident at once (0 on error).
+int batch_persistent_blocks(size_t lds)
+{
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_batch_persistent, kLanes, lds) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus / kXcds * kXcds;
+}
+
+hipError_t launch_batch_persistent(const BatchLaunch& b, int* ctl, int p0, int K, int blocks, hipStream_t s)
+{
+    const size_t lds = b.lds_r > b.lds_c ? b.lds_r : b.lds_c;
+    BatchLaunch bb = b;
+    void* args[] = {&bb, &ctl, &p0, &K};
+    return hipLaunchCooperativeKernel((const void*)k_batch_persistent, dim3(blocks), dim3(kLanes), args,
+                                      (unsigned)lds, s);
+}
 
 hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, hipStream_t s, bool cold)
 {

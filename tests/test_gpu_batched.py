@@ -120,3 +120,36 @@ def test_batched_stops_at_max_iters(dev, max_iters, check_every):
         assert np.array_equal(z_b, z_s), (k, float(np.abs(z_b - z_s).max()))
         assert np.allclose(res.x[k].cpu().numpy(), single.x.view(shapes[k]).cpu().numpy(), rtol=1e-6, atol=1e-6)
         assert res.energy[k] == single.energy
+
+
+def test_batched_persistent_matches_graph_replay(dev):
+    """One persistent launch per check period (device work queue, device-wide
+    barriers) gives the same iterates as the replayed graph of per-phase
+    launches: the same certified iterations, energies, labels and states."""
+    from paper_1503_01563_amd import mc
+    rng = np.random.default_rng(5)
+    shapes = [tuple(int(v) for v in rng.integers(20, 300, size=2)) for _ in range(12)] + [(1, 50), (3, 3)]
+    ws, As, host = batch_inputs(shapes, 4100, dev)
+    ref = mc.tv_solve_batched(ws, As, max_iters=3000, check_every=4, return_z=True)
+    per = mc.tv_solve_batched(ws, As, max_iters=3000, check_every=4, return_z=True, persistent=True)
+    assert ref.converged and per.converged
+    assert per.iters == ref.iters and per.energy == ref.energy
+    for k, (w, a) in enumerate(host):
+        assert bool((per.labels[k] == ref.labels[k]).all()), k
+        assert bool((per.z[k] == ref.z[k]).all()), k
+    for k in (0, 1, len(shapes) - 1):
+        w, a = host[k]
+        assert per.energy[k] == oracle.mincut(w, a, "dinic")[0]
+
+
+@pytest.mark.parametrize("max_iters", [3, 10])
+def test_batched_persistent_stops_at_max_iters(dev, max_iters):
+    from paper_1503_01563_amd import mc
+    shapes = [(37, 53), (64, 20), (9, 9)]
+    ws, As, host = batch_inputs(shapes, 3100, dev)
+    ref = mc.tv_solve_batched(ws, As, max_iters=max_iters, check_every=4, gap_tol=0.0, return_z=True)
+    per = mc.tv_solve_batched(ws, As, max_iters=max_iters, check_every=4, gap_tol=0.0, return_z=True,
+                              persistent=True)
+    assert per.iters == [max_iters] * len(shapes) == ref.iters
+    for k in range(len(shapes)):
+        assert bool((per.z[k] == ref.z[k]).all()), k
