@@ -224,8 +224,17 @@ def roofline(prof, n, bytes_value, bytes_duals, kernel, traffic, dual_launches_p
     }
 
 
+def progress(msg, t0=[None]):
+    """One line per finished section on stderr (the JSON line alone goes to stdout)."""
+    now = time.time()
+    if t0[0] is None:
+        t0[0] = now
+    print("bench: %s (%.1f s)" % (msg, now - t0[0]), file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
+    progress("start")
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path; "
               "run with --gpus 1", file=sys.stderr)
@@ -242,6 +251,7 @@ def main():
     n = w.size
     r = w.ndim
     results, dt, walls = timed_solves(wt, at, args.steps, args.warmup, args.check_every)
+    progress("volume: %d timed solves" % args.steps)
     if args.calibrate_copy:
         src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -282,19 +292,27 @@ def main():
     }
     if args.image:
         out["image2d"] = image2d_section(args.image_seed, (args.size, args.size), args.check_every)
+        progress("image2d")
     if args.warm_grids > 0:
         out["warm_start"] = warm_start_section(args.warm_grids)
+        progress("warm start")
         out["dual_reuse"] = dual_reuse_section()
+        progress("dual reuse")
     if args.grid8:
         out["grid8"] = grid8_section(args.image_seed, (args.size, args.size))
+        progress("grid8")
     if args.multilabel:
         out["alpha_expansion"] = alpha_expansion_section()
+        progress("alpha expansion")
     if args.mixed:
         out["mixed_outer_loop"] = mixed_outer_loop_section(args.image_seed)
+        progress("mixed outer loop")
     if args.batched:
         out["batched"] = batched_section()
+        progress("batched")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, a, last, args.cpu_seconds, full=args.cpu_full)
+        progress("cpu baseline")
     print(json.dumps(out))
 
 

@@ -80,6 +80,11 @@ extern "C" {
                                     and sweep whole chains for the rest of the solve when they are 1 in
                                     10 or more (one extra stream synchronisation); 8-connected grids
                                     use pieces */
+#define MC_DEBUG 64u             /* mc_tv_solve, 4- and 6-connected splitting: after every iteration
+                                    scan the state for NaN/Inf, and at every check assert that each
+                                    edge dual lies in its box |p| <= a and is zero where no edge
+                                    exists; a failure returns MC_ERR_NUMERIC naming the iteration
+                                    (one stream synchronisation per iteration) */
 #define MC_BATCH_PERSISTENT 32u  /* mc_tv_solve_batched: run each check period's iterations as one
                                     cooperative persistent launch (resident waves share out the work
                                     items of every unfinished grid, a device-wide barrier between the
@@ -121,7 +126,7 @@ typedef struct {
                              1e-3, 0, -1e-3, -1e-2, -1e-1, -1); the first of least energy
                              is returned (default 1e-3) */
     uint32_t flags;       /* MC_VALIDATE | MC_PROFILE | MC_WARM_MOVES | MC_WHOLE_CHAINS | MC_PIECE_CHAINS |
-                             MC_BATCH_PERSISTENT */
+                             MC_BATCH_PERSISTENT | MC_DEBUG */
     int32_t batch_items;  /* mc_tv_solve_batched: work items per sweep launch (0 = tuned) */
     int32_t bcd_iters;    /* MC_VARIANT_BCD_DR: block coordinate descent iterations (0 = 16) */
     int32_t reserved[2];  /* must be 0 */
@@ -248,8 +253,9 @@ int mc_cut_energy(mc_ctx *ctx, const mc_grid *grid, const float *w,
  * period is captured in a hipGraph and replayed; the iterations left below a
  * whole period at opts.max_iters run outside the graph, so no grid runs more
  * than opts.max_iters and every grid ends on a check.  opts.batch_items > 0
- * fixes the work items per sweep launch; 0 uses the value tuned on the first
- * solve of this batch shape.  Synchronises the stream.  Returns MC_OK when
+ * fixes the work items per sweep launch (with the default piece overlap); 0
+ * uses the work items and overlap tuned on the first solve of this batch
+ * shape (one timed iteration per candidate pair).  Synchronises the stream.  Returns MC_OK when
  * every grid is certified, MC_NOT_CONVERGED otherwise.
  */
 int mc_tv_solve_batched(mc_ctx *ctx, int n_grids, const mc_grid *grids,

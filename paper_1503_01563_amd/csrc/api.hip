@@ -227,6 +227,33 @@ int run_check(mc_ctx* c, const SolveWs& ws, const Geo& g, bool conn8, const floa
     return MC_OK;
 }
 
+// MC_DEBUG: the state after iteration `it` holds no NaN/Inf.
+int debug_state(mc_ctx* c, const SolveWs& ws, const float* z, size_t nz, int it, hipStream_t s)
+{
+    MC_HIP(launch_count_nonfinite(z, (int)nz, ws.partials, ws.dout, s));
+    MC_HIP(hipMemcpyAsync(c->hout, ws.dout, sizeof(double), hipMemcpyDeviceToHost, s));
+    MC_HIP(hipStreamSynchronize(s));
+    if (c->hout[0] > 0)
+        return fail(MC_ERR_NUMERIC, "MC_DEBUG: " + std::to_string((long long)c->hout[0]) +
+                                        " non-finite state values after iteration " + std::to_string(it));
+    return MC_OK;
+}
+
+// MC_DEBUG: the edge duals of check iteration `it` lie in their boxes and
+// vanish where no edge exists.
+int debug_duals(mc_ctx* c, const SolveWs& ws, const Geo& g, const float* const* a, const float* const* pj, int it,
+                hipStream_t s)
+{
+    MC_HIP(launch_debug_duals(g, a, pj, ws.partials, ws.dout, s));
+    MC_HIP(hipMemcpyAsync(c->hout, ws.dout, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    MC_HIP(hipStreamSynchronize(s));
+    if (c->hout[0] > 0 || c->hout[1] > 0)
+        return fail(MC_ERR_NUMERIC, "MC_DEBUG: iteration " + std::to_string(it) + ": " +
+                                        std::to_string((long long)c->hout[0]) + " edge duals outside |p| <= a, " +
+                                        std::to_string((long long)c->hout[1]) + " non-zero on a last slice");
+    return MC_OK;
+}
+
 // Labels of the last certificate's primal, optional outputs, stats.
 int finish_solve(mc_ctx* c, const SolveWs& ws, const Geo& g, const float* state, size_t nstate, float* x_out,
                  uint8_t* labels_out, float* z_out, mc_stats* stats, int it, bool converged, const CheckState& st,
@@ -585,7 +612,9 @@ int solve_split(mc_ctx* c, const SolveWs& ws, Geo g, bool two_set, const float* 
         zc = zn;
         zn = zt;
         if ((rc = probe.after_iteration(tm.launches))) return rc;
+        if ((o.flags & MC_DEBUG) && (rc = debug_state(c, ws, zc, nz, it, s))) return rc;
         if (!check) continue;
+        if ((o.flags & MC_DEBUG) && (rc = debug_duals(c, ws, g, a, pj, it, s))) return rc;
         bool done = false;
         if ((rc = run_check(c, ws, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
         if (done) {

@@ -37,7 +37,15 @@ namespace {
 constexpr size_t kAlignFloats = 64;
 constexpr int kVoxelsPerRedBlock = kReduceThreads * 8;
 constexpr int kMaxRedBlocksPerGrid = 256;
-const int kCandidates[] = {2048, 4096, 8192, 16384};
+// Autotune candidates: work items per sweep launch (which sets the piece
+// length of each grid), and the overlap the pieces scan in front of them
+// (0: by launch size, 8 or 12; a short overlap saves scan work where brackets
+// close early, a long one saves restarts where they close late).
+struct Cand {
+    int items, overlap;
+};
+const Cand kCandidates[] = {{2048, 0}, {4096, 0}, {8192, 0}, {16384, 0}, {2048, 4}, {4096, 4},
+                            {8192, 4}, {16384, 4}, {2048, 16}, {4096, 16}, {8192, 16}, {16384, 16}};
 constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 
 size_t align_floats(size_t x) { return (x + kAlignFloats - 1) / kAlignFloats * kAlignFloats; }
@@ -49,7 +57,7 @@ struct Plan {
     size_t lds_r = 0, lds_c = 0;
 };
 
-void plan_pieces(Plan& pl, const std::vector<Geo>& geos, size_t n_total, int want_total)
+void plan_pieces(Plan& pl, const std::vector<Geo>& geos, size_t n_total, int want_total, int overlap = 0)
 {
     pl.item_r.clear();
     pl.item_c.clear();
@@ -63,16 +71,16 @@ void plan_pieces(Plan& pl, const std::vector<Geo>& geos, size_t n_total, int wan
     long tot_r = 0, tot_c = 0;
     for (const Geo& g : geos) {
         const int want = want_of(g);
-        tot_r += (long)((geo_nchains(g, 0) + 63) / 64) * piece_config(g, 0, want, INT32_MAX).pieces;
-        tot_c += (long)((geo_nchains(g, 1) + 63) / 64) * piece_config(g, 1, want, INT32_MAX).pieces;
+        tot_r += (long)((geo_nchains(g, 0) + 63) / 64) * piece_config(g, 0, want, INT32_MAX, overlap).pieces;
+        tot_c += (long)((geo_nchains(g, 1) + 63) / 64) * piece_config(g, 1, want, INT32_MAX, overlap).pieces;
     }
     const int lr = (int)std::min<long>(tot_r, INT32_MAX), lc = (int)std::min<long>(tot_c, INT32_MAX);
     for (size_t gi = 0; gi < geos.size(); ++gi) {
         const Geo& g = geos[gi];
         const int want = want_of(g);
         BatchGrid& t = pl.tab[gi];
-        t.cr = piece_config(g, 0, want, lr);
-        t.cc = piece_config(g, 1, want, lc);
+        t.cr = piece_config(g, 0, want, lr, overlap);
+        t.cc = piece_config(g, 1, want, lc, overlap);
         const int groups_r = (geo_nchains(g, 0) + 63) / 64, groups_c = (geo_nchains(g, 1) + 63) / 64;
         t.item0_r = (int)pl.item_r.size();
         pl.item_r.insert(pl.item_r.end(), (size_t)groups_r * t.cr.pieces, (int)gi);
@@ -243,17 +251,20 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
         MC_HIP(hipMemsetAsync(pl.tab[gi].z[0], 0, sizeof(float) * (size_t)geos[gi].n, s));
 
     const unsigned long long sig = signature(geos);
-    int items = o.batch_items > 0 ? o.batch_items : 0;
+    int items = o.batch_items > 0 ? o.batch_items : 0, overlap = 0;
     auto it_tuned = c->tuned_items.find(sig);
-    if (items == 0 && it_tuned != c->tuned_items.end()) items = it_tuned->second;
+    if (items == 0 && it_tuned != c->tuned_items.end()) {
+        items = it_tuned->second.first;
+        overlap = it_tuned->second.second;
+    }
 
     // metadata for the largest plan that may be used, header first
-    std::vector<int> cands;
+    std::vector<Cand> cands;
     if (items == 0) cands.assign(kCandidates, kCandidates + kNumCandidates);
-    else cands.push_back(items);
+    else cands.push_back({items, overlap});
     size_t need = 0;
-    for (int cand : cands) {
-        plan_pieces(pl, geos, n_total, cand);
+    for (const Cand& cand : cands) {
+        plan_pieces(pl, geos, n_total, cand.items, cand.overlap);
         size_t a1, a2, a3, a4;
         need = std::max(need, plan_bytes(pl, &a1, &a2, &a3, &a4));
     }
@@ -271,7 +282,8 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
     // columns).  The iterations before the replays leave at least one for
     // the last check.
     if (o.max_iters > 1) {
-        plan_pieces(pl, geos, n_total, items > 0 ? items : kCandidates[0]);
+        if (items > 0) plan_pieces(pl, geos, n_total, items, overlap);
+        else plan_pieces(pl, geos, n_total, kCandidates[0].items, kCandidates[0].overlap);
         if ((rc = upload(c, pl, s, &bl, &partials))) return rc;
         MC_HIP(launch_batch_iteration(bl, 0, false, s, true));
         ++it;
@@ -279,9 +291,9 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
     if (items == 0) {
         // autotune on the first iterations of the solve itself
         float best_ms = INFINITY;
-        int best = kCandidates[0];
+        Cand best = kCandidates[0];
         for (int k = 0; k < kNumCandidates && it + 1 < o.max_iters; ++k) {
-            plan_pieces(pl, geos, n_total, kCandidates[k]);
+            plan_pieces(pl, geos, n_total, kCandidates[k].items, kCandidates[k].overlap);
             if ((rc = upload(c, pl, s, &bl, &partials))) return rc;
             MC_HIP(hipEventRecord(c->ev0, s));
             MC_HIP(launch_batch_iteration(bl, it & 1, false, s));
@@ -295,8 +307,9 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
             }
             ++it;
         }
-        items = best;
-        if (best_ms < INFINITY) c->tuned_items[sig] = best;  // (no candidate timed: nothing learnt)
+        items = best.items;
+        overlap = best.overlap;
+        if (best_ms < INFINITY) c->tuned_items[sig] = {items, overlap};  // (no candidate timed: nothing learnt)
     } else {
         // as many iterations as the autotuner runs, so that every call checks
         // at the same iterations (and reports the same results) whether it
@@ -306,7 +319,7 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
             ++it;
         }
     }
-    plan_pieces(pl, geos, n_total, items);
+    plan_pieces(pl, geos, n_total, items, overlap);
     if ((rc = upload(c, pl, s, &bl, &partials))) return rc;
     // checks at multiples of K, as mc_tv_solve checks at multiples of check_every
     for (; it % K != 0 && it + 1 < o.max_iters; ++it) MC_HIP(launch_batch_iteration(bl, it & 1, false, s));

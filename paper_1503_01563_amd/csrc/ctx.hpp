@@ -35,7 +35,8 @@ struct mc_ctx {
     char* bmeta = nullptr;           // table, maps, partials, counters
     int* bctl = nullptr;             // persistent batch launch control words (fine-grained memory)
     std::map<size_t, int> persist_blocks;  // LDS bytes -> workgroups found resident at once
-    std::map<unsigned long long, int> tuned_items;  // batch signature -> work items per launch
+    std::map<unsigned long long, std::pair<int, int>> tuned_items;  // batch signature -> work items per
+                                                                    // launch, piece overlap (0: by mode)
 
     // 8-connected grids: prox outputs of the four families, straightened zig-zag chains
     size_t g8cap = 0;       // floats in g8buf

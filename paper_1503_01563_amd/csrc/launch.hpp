@@ -40,8 +40,9 @@ struct PieceCfg {
 // launch_items is the number of work items of the whole launch the family is
 // part of (0: this family alone); launches of at most kLatencyItems items run
 // about one wave per SIMD and get a longer overlap (12 instead of 8), so that
-// almost no piece has to restart its scans.
-PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items);
+// almost no piece has to restart its scans.  overlap > 0 sets the overlap
+// instead (the batched autotuner's candidates).
+PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items, int overlap = 0);
 constexpr int kDefaultItems = 4096;
 constexpr int kLatencyItems = 2048;
 // dynamic LDS bytes of a sweep launch with these pieces
@@ -203,6 +204,11 @@ hipError_t launch_energy(const Geo& g, const float* w, const float* const* a,
 // out[1] = #non-finite values in w and a.
 hipError_t launch_validate(const Geo& g, const float* w, const float* const* a,
                            double* partials, double* out, hipStream_t s);
+
+// MC_DEBUG: out[0] = duals outside |p_j| <= a_j (or not finite), out[1] =
+// non-zero duals on a family's last slice.
+hipError_t launch_debug_duals(const Geo& g, const float* const* a, const float* const* p, double* partials,
+                              double* out, hipStream_t s);
 
 // Non-finite entries in an array (out[0]).
 hipError_t launch_count_nonfinite(const float* x, int n, double* partials, double* out,

@@ -599,6 +599,27 @@ k_validate(Geo g, const float* __restrict__ w, Ptr3 a, double* __restrict__ part
     block_reduce_store<2>(v, partials + (size_t)blockIdx.x * 2);
 }
 
+// Debug checks of the edge duals of a check iteration: out[0] = duals
+// outside their box |p_j| <= a_j (or not finite), out[1] = non-zero duals on
+// a family's last slice, where no edge exists.
+__global__ void __launch_bounds__(kReduceThreads)
+k_debug_duals(Geo g, Ptr3 a, Ptr3 p, double* __restrict__ partials)
+{
+    double out_box = 0.0, on_last = 0.0;
+    for (Walk k(g); k.i < g.n; k.next(g)) {
+        const int i = k.i;
+        const int cc[3] = {k.c.x, k.c.y, k.c.d};
+        const int ext[3] = {g.W, g.H, g.D};
+        for (int j = 0; j < g.ndim; ++j) {
+            const float pj = p.p[j][i], aj = a.p[j][i];
+            if (!(fabsf(pj) <= aj)) out_box += 1.0;
+            if (cc[j] + 1 == ext[j] && pj != 0.f) on_last += 1.0;
+        }
+    }
+    double v[2] = {out_box, on_last};
+    block_reduce_store<2>(v, partials + (size_t)blockIdx.x * 2);
+}
+
 __global__ void __launch_bounds__(kReduceThreads)
 k_count_nonfinite(const float* __restrict__ x, int n, double* __restrict__ partials)
 {
@@ -816,6 +837,20 @@ hipError_t launch_ml_energy(const Geo& g, const float* data, const float* const*
     hipLaunchKernelGGL(k_ml_energy, dim3(nb), dim3(kReduceThreads), 0, s, g, data, lam[0], lam[1], kind, trunc, f,
                        partials);
     hipLaunchKernelGGL(k_finalize<1>, dim3(1), dim3(kReduceThreads), 0, s, partials, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_duals(const Geo& g, const float* const* a, const float* const* p, double* partials,
+                             double* out, hipStream_t s)
+{
+    const int nb = reduce_blocks(g.n);
+    Ptr3 pa, pp;
+    for (int j = 0; j < 3; ++j) {
+        pa.p[j] = j < g.ndim ? a[j] : nullptr;
+        pp.p[j] = j < g.ndim ? p[j] : nullptr;
+    }
+    hipLaunchKernelGGL(k_debug_duals, dim3(nb), dim3(kReduceThreads), 0, s, g, pa, pp, partials);
+    hipLaunchKernelGGL(k_finalize<2>, dim3(1), dim3(kReduceThreads), 0, s, partials, nb, out);
     return hipGetLastError();
 }
 

@@ -986,7 +986,7 @@ hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, 
 size_t piece_lds_bytes(const PieceCfg& cfg) { return lds_bytes(cfg); }
 
 
-PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items)
+PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items, int overlap)
 {
     // about `want` work items, pieces of 16 to kMaxLen positions (a work item's
     // LDS, 2 x (reach_lo + len + reach_hi) x 65 floats, stays below 64 KiB)
@@ -1009,7 +1009,7 @@ PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items)
     // short and LDS small (more waves resident).
     const long items = launch_items > 0 ? launch_items : (long)groups * cfg.pieces;
     const bool latency_bound = items <= kLatencyItems;
-    cfg.overlap = cut ? (latency_bound ? 12 : 8) : 0;
+    cfg.overlap = cut ? (overlap > 0 ? overlap : (latency_bound ? 12 : 8)) : 0;
     cfg.tail = cut ? 8 : 0;
     // LDS: the overlap plus the weight of the edge in front of it, the piece,
     // and the tail -- plus one block of tail growth when latency bound (with

@@ -232,6 +232,29 @@ def test_validation_errors(dev):
         mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], variant=1, max_iters=0)
 
 
+@pytest.mark.parametrize("shape", [(40, 57), (9, 20, 23)])
+def test_debug_flag_checks_and_changes_nothing(dev, shape):
+    """MC_DEBUG on valid input: the same iterates and results as without it
+    (its checks only read).  With a NaN unary (not validated) it stops at
+    iteration 1 with MC_ERR_NUMERIC naming the iteration, where the plain
+    solve only notices at its first certificate."""
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid(shape, 77)
+    tw, ta = to_dev(w, dev), [to_dev(x, dev) for x in a]
+    ref = mc.tv_solve(tw, ta, max_iters=400, check_every=3, return_z=True)
+    dbg = mc.tv_solve(tw, ta, max_iters=400, check_every=3, return_z=True, debug=True)
+    assert dbg.converged and dbg.iters == ref.iters and dbg.energy == ref.energy
+    assert bool((dbg.z == ref.z).all()) and bool((dbg.labels == ref.labels).all())
+    wn = w.copy()
+    wn.flat[w.size // 2] = np.nan
+    with pytest.raises(mc.McError) as e:
+        mc.tv_solve(to_dev(wn, dev), ta, max_iters=50, check_every=10, debug=True)
+    assert e.value.code == -6 and "after iteration 1" in str(e.value)
+    with pytest.raises(mc.McError) as e:
+        mc.tv_solve(to_dev(wn, dev), ta, max_iters=50, check_every=10)
+    assert e.value.code == -6
+
+
 def test_image2d_full_size_exact(dev):
     """Segmentation-shaped 1024x1024 grid: exact energy against max-flow."""
     from paper_1503_01563_amd import mc
