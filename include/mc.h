@@ -85,6 +85,10 @@ extern "C" {
                                     edge dual lies in its box |p| <= a and is zero where no edge
                                     exists; a failure returns MC_ERR_NUMERIC naming the iteration
                                     (one stream synchronisation per iteration) */
+#define MC_FP64_STATE 128u       /* mc_tv_solve, 4- and 6-connected grids, variants AUTO, TWO_SET and
+                                    PRODUCT (debug): the same splitting with its state, chain proxes
+                                    and averaging in FP64 (one lane per whole chain: slow); the
+                                    certificate, x_out and z_out as usual (z_out rounded to FP32) */
 #define MC_BATCH_PERSISTENT 32u  /* mc_tv_solve_batched: run each check period's iterations as one
                                     cooperative persistent launch (resident waves share out the work
                                     items of every unfinished grid, a device-wide barrier between the
@@ -126,7 +130,7 @@ typedef struct {
                              1e-3, 0, -1e-3, -1e-2, -1e-1, -1); the first of least energy
                              is returned (default 1e-3) */
     uint32_t flags;       /* MC_VALIDATE | MC_PROFILE | MC_WARM_MOVES | MC_WHOLE_CHAINS | MC_PIECE_CHAINS |
-                             MC_BATCH_PERSISTENT | MC_DEBUG */
+                             MC_BATCH_PERSISTENT | MC_DEBUG | MC_FP64_STATE */
     int32_t batch_items;  /* mc_tv_solve_batched: work items per sweep launch (0 = tuned) */
     int32_t bcd_iters;    /* MC_VARIANT_BCD_DR: block coordinate descent iterations (0 = 16) */
     int32_t reserved[2];  /* must be 0 */

@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libmc.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
 SOURCES = ["sweeps.hip", "reduce.hip", "api.hip", "batch.hip", "convnet.hip", "grid8.hip", "variants.hip",
-           "multilabel.hip"]
+           "multilabel.hip", "fp64.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

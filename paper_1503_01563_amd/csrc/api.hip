@@ -535,6 +535,78 @@ int scratch_setup(int device)
     return MC_OK;
 }
 
+// MC_FP64_STATE: the splitting of solve_split with its state, chain proxes
+// and averaging in FP64 (fp64.hip); the duals of check iterations are
+// written as clipped FP32 into ws.p and certified as usual.
+int solve_fp64(mc_ctx* c, const SolveWs& ws, Geo g, bool two_set, const float* w, const float* const* a,
+               const float* z0, float* x_out, uint8_t* labels_out, float* z_out, mc_stats* stats, const mc_opts& o,
+               hipStream_t s)
+{
+    int rc;
+    const int r = g.ndim;
+    const size_t n = (size_t)g.n;
+    const size_t nz = two_set ? n : (size_t)r * n;
+    const size_t need = 3 * nz;  // state, next state, prox outputs (n for the rows or r n)
+    if (need > c->d64cap) {
+        MC_HIP(hipStreamSynchronize(s));
+        (void)hipFree(c->d64buf);
+        c->d64buf = nullptr;
+        c->d64cap = 0;
+        if (hipMalloc(&c->d64buf, sizeof(double) * need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MC_ERR_NOMEM, "FP64 state allocation failed");
+        }
+        c->d64cap = need;
+    }
+    double* zc = c->d64buf;
+    double* zn = zc + nz;
+    double* q = zn + nz;
+    if (o.flags & MC_VALIDATE) {
+        MC_HIP(launch_validate(g, w, a, ws.partials, ws.dout, s));
+        MC_HIP(hipMemcpyAsync(c->hout, ws.dout, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        MC_HIP(hipStreamSynchronize(s));
+        if (c->hout[1] > 0) return fail(MC_ERR_NONFINITE, "non-finite value in w or a");
+        if (c->hout[0] > 0) return fail(MC_ERR_NEGATIVE_WEIGHT, "negative weight or non-zero weight on a last slice");
+    }
+    if (z0) MC_HIP(launch_f32_to_f64(nz, z0, zc, s));
+    else MC_HIP(hipMemsetAsync(zc, 0, sizeof(double) * nz, s));
+    MC_HIP(hipEventRecord(c->ev0, s));
+    const float* pj[3] = {ws.p, ws.p + n, ws.p + 2 * n};
+    SweepTimer tm{c, false};
+    float taus[kNumTau];
+    tau_ladder(o.tau0, taus);
+    CheckState st;
+    int it = 0;
+    bool converged = false;
+    while (it < o.max_iters) {
+        ++it;
+        const bool check = (it % o.check_every == 0) || it == o.max_iters;
+        if (two_set) {
+            MC_HIP(launch_dr2_rows64(g, zc, a[0], q, check ? ws.p : nullptr, s));
+            MC_HIP(launch_dr2_cols64(g, q, zc, zn, w, a[1], check ? ws.p + n : nullptr, s));
+        } else {
+            for (int j = 0; j < r; ++j)
+                MC_HIP(launch_family64(g, j, zc + (size_t)j * n, a[j], q + (size_t)j * n,
+                                       check ? ws.p + (size_t)j * n : nullptr, s));
+            MC_HIP(launch_combine64(n, r, zc, q, w, zn, s));
+        }
+        double* zt = zc;
+        zc = zn;
+        zn = zt;
+        tm.launches += two_set ? 2 : r;
+        if (!check) continue;
+        bool done = false;
+        if ((rc = run_check(c, ws, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
+        if (done) {
+            converged = true;
+            break;
+        }
+    }
+    MC_HIP(launch_f64_to_f32(nz, zc, ws.z, s));  // the state, rounded, for z_out
+    g.whole = 1;
+    return finish_solve(c, ws, g, ws.z, nz, x_out, labels_out, z_out, stats, it, converged, st, tm, s);
+}
+
 // The splitting method on a 4- or 6-connected grid (two-set form or product
 // space) with the device buffers of ws; arguments already checked.
 int solve_split(mc_ctx* c, const SolveWs& ws, Geo g, bool two_set, const float* w, const float* const* a,
@@ -710,6 +782,7 @@ int mc_ctx_destroy(mc_ctx* c)
     (void)hipFree(c->nbuf);
     (void)hipFree(c->g8buf);
     (void)hipFree(c->vbuf);
+    (void)hipFree(c->d64buf);
     (void)hipFree(c->mlbuf);
     (void)hipFree(c->mlsel);
     if (c->bstream) (void)hipStreamDestroy(c->bstream);
@@ -766,6 +839,10 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     mc_opts o;
     if ((rc = read_opts(opts_in, o))) return rc;
     g.whole = (o.flags & MC_WHOLE_CHAINS) ? 1 : 0;
+    if ((o.flags & MC_FP64_STATE) &&
+        (grid->conn == 8 || (o.variant != MC_VARIANT_AUTO && o.variant != MC_VARIANT_TWO_SET &&
+                             o.variant != MC_VARIANT_PRODUCT)))
+        return fail(MC_ERR_INVALID_ARG, "MC_FP64_STATE: 4- and 6-connected grids, variants AUTO, TWO_SET, PRODUCT");
     if (grid->conn == 8) {
         if (g.ndim != 2) return fail(MC_ERR_INVALID_ARG, "8-connected grids are 2D");
         if (o.variant == MC_VARIANT_TWO_SET) return fail(MC_ERR_INVALID_ARG, "8-connected grids use the product space");
@@ -828,6 +905,9 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     const int r = g.ndim;
     const size_t n = (size_t)g.n;
     if ((rc = ensure_ws(c, n, r))) return rc;
+    if (o.flags & MC_FP64_STATE)
+        return solve_fp64(c, ctx_ws(c), g, two_set, w, a, z0, x_out, labels_out, z_out, stats, o,
+                          (hipStream_t)stream);
     return solve_split(c, ctx_ws(c), g, two_set, w, a, z0, x_out, labels_out, z_out, stats, o,
                        (hipStream_t)stream);
 }
@@ -847,6 +927,8 @@ int mc_tv_solve_noalloc(mc_ctx* c, const mc_grid* grid, const float* w, const fl
     if ((rc = read_opts(opts_in, o))) return rc;
     if (grid->conn == 8) return fail(MC_ERR_INVALID_ARG, "mc_tv_solve_noalloc: 4- and 6-connected grids only");
     if (o.flags & MC_PROFILE) return fail(MC_ERR_INVALID_ARG, "mc_tv_solve_noalloc: MC_PROFILE needs timing events");
+    if (o.flags & MC_FP64_STATE)
+        return fail(MC_ERR_INVALID_ARG, "mc_tv_solve_noalloc: MC_FP64_STATE allocates its FP64 state");
     bool two_set;
     if (o.variant == MC_VARIANT_AUTO) two_set = g.ndim == 2;
     else if (o.variant == MC_VARIANT_TWO_SET) two_set = true;

@@ -42,6 +42,10 @@ struct mc_ctx {
     size_t g8cap = 0;       // floats in g8buf
     float* g8buf = nullptr;
 
+    // MC_FP64_STATE: z, z2, q of the FP64 iteration (3 * r * n doubles)
+    size_t d64cap = 0;      // doubles in d64buf
+    double* d64buf = nullptr;
+
     // other outer iterations (BCD, AP, FISTA)
     size_t vcap = 0;        // floats in vbuf
     float* vbuf = nullptr;

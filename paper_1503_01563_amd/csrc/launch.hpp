@@ -106,6 +106,19 @@ hipError_t launch_zz_gather(int H, int W, const float* z2, const float* z3, cons
 // null, the diagonal and anti-diagonal duals per cell.
 hipError_t launch_zz_scatter(int H, int W, const float* z2, const float* z3, const float* zx, const float* zp,
                              float* q2, float* q3, float* pdd, float* pad, hipStream_t s);
+// ---- FP64 state (MC_FP64_STATE, fp64.hip): one lane per whole chain ----------
+// Duals (nullable) are written as FP32 clipped to their boxes.
+hipError_t launch_dr2_rows64(const Geo& g, const double* z, const float* a_x, double* q1, float* p1, hipStream_t s);
+hipError_t launch_dr2_cols64(const Geo& g, const double* q1, const double* z, double* znew, const float* w,
+                             const float* a_y, float* p2, hipStream_t s);
+hipError_t launch_family64(const Geo& g, int axis, const double* z, const float* a, double* q, float* p,
+                           hipStream_t s);
+// z_j' = y_j - (2Y - Z + w) / r for r = 2 or 3 families
+hipError_t launch_combine64(size_t n, int r, const double* z, const double* q, const float* w, double* zn,
+                            hipStream_t s);
+hipError_t launch_f32_to_f64(size_t n, const float* x, double* y, hipStream_t s);
+hipError_t launch_f64_to_f32(size_t n, const double* x, float* y, hipStream_t s);
+
 // Product-space averaging over four families: zn_j = y_j - (2Y - Z + w)/4.
 hipError_t launch_combine4(size_t n, const float* z, const float* q, const float* w, float* zn, hipStream_t s);
 // z_j' = y_j - (2Y - Z + w) / 3 for a volume's three families

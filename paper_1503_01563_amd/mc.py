@@ -32,6 +32,7 @@ MC_WHOLE_CHAINS = 8
 MC_PIECE_CHAINS = 16
 MC_BATCH_PERSISTENT = 32
 MC_DEBUG = 64
+MC_FP64_STATE = 128
 VARIANT_AUTO, VARIANT_TWO_SET, VARIANT_PRODUCT = 0, 1, 2
 VARIANT_BCD, VARIANT_AP, VARIANT_FISTA = 3, 4, 5
 VARIANT_BCD_DR = 6
@@ -216,9 +217,10 @@ class SolveResult:
 
 
 def make_opts(max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
-              validate=False, profile=False, whole_chains=None, debug=False):
+              validate=False, profile=False, whole_chains=None, debug=False, fp64_state=False):
     """whole_chains: None = chosen by the solver from its first sweeps, True =
-    whole-chain sweeps, False = overlapping pieces.  debug: MC_DEBUG."""
+    whole-chain sweeps, False = overlapping pieces.  debug: MC_DEBUG.
+    fp64_state: MC_FP64_STATE."""
     o = Opts()
     load_library().mc_opts_default(ctypes.byref(o))
     o.max_iters = int(max_iters)
@@ -226,7 +228,8 @@ def make_opts(max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, 
     o.gap_tol = float(gap_tol)
     o.variant = int(variant)
     o.tau0 = float(tau0)
-    o.flags = (MC_VALIDATE if validate else 0) | (MC_PROFILE if profile else 0) | (MC_DEBUG if debug else 0)
+    o.flags = ((MC_VALIDATE if validate else 0) | (MC_PROFILE if profile else 0) | (MC_DEBUG if debug else 0)
+               | (MC_FP64_STATE if fp64_state else 0))
     if whole_chains is not None:
         o.flags |= MC_WHOLE_CHAINS if whole_chains else MC_PIECE_CHAINS
     return o
@@ -235,11 +238,12 @@ def make_opts(max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, 
 def tv_solve(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tensor] = None,
              max_iters=500, check_every=1, gap_tol=1e-3, variant=VARIANT_AUTO, tau0=1e-3,
              validate=False, return_x=True, return_z=False, labels_out=None,
-             profile=False, whole_chains=None, debug=False) -> SolveResult:
+             profile=False, whole_chains=None, debug=False, fp64_state=False) -> SolveResult:
     """Minimum cut of one grid by mc_tv_solve.  debug: MC_DEBUG (state and
-    dual checks every iteration; 4- and 6-connected splitting solves)."""
+    dual checks every iteration; 4- and 6-connected splitting solves).
+    fp64_state: MC_FP64_STATE (the splitting in FP64, a slow debug path)."""
     return _solve("mc_tv_solve", w, a, z0, max_iters, check_every, gap_tol, variant, tau0, validate,
-                  return_x, return_z, labels_out, profile, whole_chains, debug)
+                  return_x, return_z, labels_out, profile, whole_chains, debug, fp64_state)
 
 
 def tv_solve_noalloc(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[torch.Tensor] = None,
@@ -254,7 +258,7 @@ def tv_solve_noalloc(w: torch.Tensor, a: Sequence[torch.Tensor], z0: Optional[to
 
 
 def _solve(entry, w, a, z0, max_iters, check_every, gap_tol, variant, tau0, validate, return_x, return_z,
-           labels_out, profile, whole_chains, debug=False) -> SolveResult:
+           labels_out, profile, whole_chains, debug=False, fp64_state=False) -> SolveResult:
     lib = load_library()
     shape = tuple(w.shape)
     nd = len(shape)
@@ -275,7 +279,8 @@ def _solve(entry, w, a, z0, max_iters, check_every, gap_tol, variant, tau0, vali
     x = torch.empty(shape, dtype=torch.float32, device=w.device) if return_x else None
     z = torch.empty(nz, dtype=torch.float32, device=w.device) if return_z else None
     st = Stats()
-    o = make_opts(max_iters, check_every, gap_tol, variant, tau0, validate, profile, whole_chains, debug)
+    o = make_opts(max_iters, check_every, gap_tol, variant, tau0, validate, profile, whole_chains, debug,
+                  fp64_state)
     rc = getattr(lib, entry)(context(dev), ctypes.byref(_grid(shape, conn)), wp,
                          ctypes.cast(ap, ctypes.c_void_p), z0p,
                          ctypes.c_void_p(x.data_ptr()) if x is not None else None,

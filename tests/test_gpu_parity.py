@@ -255,6 +255,47 @@ def test_debug_flag_checks_and_changes_nothing(dev, shape):
     assert e.value.code == -6
 
 
+@pytest.mark.parametrize("shape,variant", [((33, 47), 1), ((20, 30), 2), ((6, 17, 19), 2)])
+def test_fp64_state_iterates_match_oracle(dev, shape, variant):
+    """MC_FP64_STATE runs the same splitting in FP64: after 150 iterations its
+    state (rounded to FP32 on output) equals the FP64 oracle's to the FP32
+    rounding of the output; the FP32 path's distance is printed beside it."""
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid(shape, 11)
+    tw, ta = to_dev(w, dev), [to_dev(x, dev) for x in a]
+    iters = 150
+    kw = dict(max_iters=iters, check_every=iters, gap_tol=0.0, variant=variant, return_z=True)
+    r64 = mc.tv_solve(tw, ta, fp64_state=True, **kw)
+    r32 = mc.tv_solve(tw, ta, **kw)
+    ro = oracle.dr_solve(w, a, variant=variant - 1, max_iters=iters, gap_tol=0, return_z=True)
+    zo = ro["z"]
+    e64 = rel_linf(r64.z.cpu().numpy(), zo)
+    e32 = rel_linf(r32.z.cpu().numpy(), zo)
+    print("%s variant %d: FP64 state %.2e, FP32 state %.2e from the oracle after %d iterations"
+          % (shape, variant, e64, e32, iters))
+    assert r64.iters == iters
+    assert e64 <= 2e-7
+
+
+@pytest.mark.parametrize("shape", [(40, 50), (8, 12, 14)])
+def test_fp64_state_exact_cut(dev, shape):
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid(shape, 12)
+    res = mc.tv_solve(to_dev(w, dev), [to_dev(x, dev) for x in a], max_iters=3000, check_every=2,
+                      fp64_state=True)
+    assert res.converged and res.energy == oracle.mincut(w, a, "dinic")[0]
+
+
+def test_fp64_state_rejections(dev):
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid((9, 11), 13)
+    tw, ta = to_dev(w, dev), [to_dev(x, dev) for x in a]
+    for kw in (dict(variant=mc.VARIANT_BCD), dict(variant=mc.VARIANT_FISTA)):
+        with pytest.raises(mc.McError) as e:
+            mc.tv_solve(tw, ta, fp64_state=True, **kw)
+        assert e.value.code == -1
+
+
 def test_image2d_full_size_exact(dev):
     """Segmentation-shaped 1024x1024 grid: exact energy against max-flow."""
     from paper_1503_01563_amd import mc
