@@ -734,18 +734,33 @@ inline size_t lds_bytes(const PieceCfg& cfg)
     return sizeof(float) * 2 * (size_t)(cfg.reach_lo + cfg.len + cfg.reach_hi + 2) * kPad;
 }
 
+// Volumes in throughput mode: overlap 4 and no staged tail.  The window of a
+// 32-position piece is then 39 LDS rows (20.3 KB per wave), which lets 8
+// waves per CU be resident instead of 6; the scans wait on the wider
+// residency less than the extra restarts and the tails read from global
+// memory cost (volume solve 75.8 -> 68.9 ms; overlap 5 or 8 at 7 waves:
+// 71.0, 71.6 ms).  On the 64-grid batch the same pieces were slower, so the
+// other launches keep 8 and 8.  The sweeps that count restarts (the solve's
+// first, which choose between pieces and whole chains) keep the default
+// overlap: early iterations have long constant segments, and with overlap 4
+// about 1 lane in 10 restarts there (the threshold of that choice) against
+// 0.4 % later on (simulated on the volume's states).
+constexpr int kVolOverlap = 4, kVolTail = 0;
+
 // the launch of k_sweep_triple with the latency / throughput mode decided on
-// its total number of work items
+// its total number of work items; in throughput mode, overlap / tail >= 0
+// replace the defaults
 template <class M2, bool kRows2>
 hipError_t launch_triple(const Geo& g, const ModeSweepP& m0, const ModeSweepP& m1, const Geo& g2, int axis2,
-                         const M2& m2, bool duals, hipStream_t s)
+                         const M2& m2, bool duals, hipStream_t s, int overlap = 0, int tail = -1)
 {
     PieceCfg c0 = piece_config(g, 0, kDefaultItems, 0), c1 = piece_config(g, 1, kDefaultItems, 0),
              c2 = piece_config(g2, axis2, kDefaultItems, 0);
     const int tot = items_of(g, 0, c0) + items_of(g, 1, c1) + items_of(g2, axis2, c2);
-    c0 = piece_config(g, 0, kDefaultItems, tot);
-    c1 = piece_config(g, 1, kDefaultItems, tot);
-    c2 = piece_config(g2, axis2, kDefaultItems, tot);
+    const bool thr = tot > kLatencyItems;
+    c0 = piece_config(g, 0, kDefaultItems, tot, thr ? overlap : 0, thr ? tail : -1);
+    c1 = piece_config(g, 1, kDefaultItems, tot, thr ? overlap : 0, thr ? tail : -1);
+    c2 = piece_config(g2, axis2, kDefaultItems, tot, thr ? overlap : 0, thr ? tail : -1);
     const int n0 = items_of(g, 0, c0), n1 = items_of(g, 1, c1), n2 = items_of(g2, axis2, c2);
     size_t shm = lds_bytes(c0);
     if (lds_bytes(c1) > shm) shm = lds_bytes(c1);
@@ -986,7 +1001,7 @@ hipError_t launch_batch_iteration(const BatchLaunch& b, int parity, bool duals, 
 size_t piece_lds_bytes(const PieceCfg& cfg) { return lds_bytes(cfg); }
 
 
-PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items, int overlap)
+PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items, int overlap, int tail)
 {
     // about `want` work items, pieces of 16 to kMaxLen positions (a work item's
     // LDS, 2 x (reach_lo + len + reach_hi) x 65 floats, stays below 64 KiB)
@@ -1010,7 +1025,7 @@ PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items, int ov
     const long items = launch_items > 0 ? launch_items : (long)groups * cfg.pieces;
     const bool latency_bound = items <= kLatencyItems;
     cfg.overlap = cut ? (overlap > 0 ? overlap : (latency_bound ? 12 : 8)) : 0;
-    cfg.tail = cut ? 8 : 0;
+    cfg.tail = cut ? (tail >= 0 ? tail : 8) : 0;
     // LDS: the overlap plus the weight of the edge in front of it, the piece,
     // and the tail -- plus one block of tail growth when latency bound (with
     // many work items, LDS per wave sets how many waves are resident)
@@ -1093,7 +1108,9 @@ hipError_t launch_sweeps3(const Geo& g, const float* z, const float* const* a, f
     }
     ModeSweepP m0{z, a[0], q, p};
     ModeSweepP m1{z + n, a[1], q + n, p ? p + n : nullptr};
-    return launch_triple<ModeSweepP, false>(g, m0, m1, g, 2, m2, p != nullptr, s);
+    const bool probe = g.restarts != nullptr;
+    return launch_triple<ModeSweepP, false>(g, m0, m1, g, 2, m2, p != nullptr, s, probe ? 0 : kVolOverlap,
+                                            probe ? -1 : kVolTail);
 }
 
 hipError_t launch_drp_final(const Geo& g, int r, const float* z, float* znew, const float* q,
