@@ -734,33 +734,41 @@ inline size_t lds_bytes(const PieceCfg& cfg)
     return sizeof(float) * 2 * (size_t)(cfg.reach_lo + cfg.len + cfg.reach_hi + 2) * kPad;
 }
 
-// Volumes in throughput mode: overlap 4 and no staged tail.  The window of a
-// 32-position piece is then 39 LDS rows (20.3 KB per wave), which lets 8
-// waves per CU be resident instead of 6; the scans wait on the wider
-// residency less than the extra restarts and the tails read from global
-// memory cost (volume solve 75.8 -> 68.9 ms; overlap 5 or 8 at 7 waves:
-// 71.0, 71.6 ms).  On the 64-grid batch the same pieces were slower, so the
-// other launches keep 8 and 8.  The sweeps that count restarts (the solve's
+// Volumes in throughput mode: 16-position pieces (about 8192 work items per
+// family), overlap 4 and no staged tail.  The window is then 23 LDS rows
+// (12 KB per wave), and residency is set by the registers (12 waves per CU)
+// instead of by LDS (6 with the default 32-position pieces, overlap and tail
+// 8): the scans hide their stalls behind the extra waves more than the extra
+// restarts, overlap and tail reads from global memory cost.  Volume solve:
+// 75.8 ms with the defaults; 68.8 ms with 32-position pieces, overlap 4 and no
+// tail (8 waves); 67.6 ms with 24-position pieces (10 waves); 67.2 ms with
+// 16 (overlap 5 or 8 at 7 waves: 71.0, 71.6 ms).  On the 64-grid batch
+// overlap 4 and no tail were slower, so the other launches keep 8 and 8.  The sweeps that count restarts (the solve's
 // first, which choose between pieces and whole chains) keep the default
 // overlap: early iterations have long constant segments, and with overlap 4
 // about 1 lane in 10 restarts there (the threshold of that choice) against
 // 0.4 % later on (simulated on the volume's states).
-constexpr int kVolOverlap = 4, kVolTail = 0;
+constexpr int kVolOverlap = 4, kVolTail = 0, kVolItems = 8192;
 
 // the launch of k_sweep_triple with the latency / throughput mode decided on
-// its total number of work items; in throughput mode, overlap / tail >= 0
-// replace the defaults
+// its total number of work items; in throughput mode, want > 0 (work items
+// per family) and overlap / tail >= 0 replace the defaults
 template <class M2, bool kRows2>
 hipError_t launch_triple(const Geo& g, const ModeSweepP& m0, const ModeSweepP& m1, const Geo& g2, int axis2,
-                         const M2& m2, bool duals, hipStream_t s, int overlap = 0, int tail = -1)
+                         const M2& m2, bool duals, hipStream_t s, int want = 0, int overlap = 0, int tail = -1)
 {
     PieceCfg c0 = piece_config(g, 0, kDefaultItems, 0), c1 = piece_config(g, 1, kDefaultItems, 0),
              c2 = piece_config(g2, axis2, kDefaultItems, 0);
-    const int tot = items_of(g, 0, c0) + items_of(g, 1, c1) + items_of(g2, axis2, c2);
+    int tot = items_of(g, 0, c0) + items_of(g, 1, c1) + items_of(g2, axis2, c2);
     const bool thr = tot > kLatencyItems;
-    c0 = piece_config(g, 0, kDefaultItems, tot, thr ? overlap : 0, thr ? tail : -1);
-    c1 = piece_config(g, 1, kDefaultItems, tot, thr ? overlap : 0, thr ? tail : -1);
-    c2 = piece_config(g2, axis2, kDefaultItems, tot, thr ? overlap : 0, thr ? tail : -1);
+    const int wi = thr && want > 0 ? want : kDefaultItems;
+    if (wi != kDefaultItems) {
+        c0 = piece_config(g, 0, wi, 0), c1 = piece_config(g, 1, wi, 0), c2 = piece_config(g2, axis2, wi, 0);
+        tot = items_of(g, 0, c0) + items_of(g, 1, c1) + items_of(g2, axis2, c2);
+    }
+    c0 = piece_config(g, 0, wi, tot, thr ? overlap : 0, thr ? tail : -1);
+    c1 = piece_config(g, 1, wi, tot, thr ? overlap : 0, thr ? tail : -1);
+    c2 = piece_config(g2, axis2, wi, tot, thr ? overlap : 0, thr ? tail : -1);
     const int n0 = items_of(g, 0, c0), n1 = items_of(g, 1, c1), n2 = items_of(g2, axis2, c2);
     size_t shm = lds_bytes(c0);
     if (lds_bytes(c1) > shm) shm = lds_bytes(c1);
@@ -1109,8 +1117,8 @@ hipError_t launch_sweeps3(const Geo& g, const float* z, const float* const* a, f
     ModeSweepP m0{z, a[0], q, p};
     ModeSweepP m1{z + n, a[1], q + n, p ? p + n : nullptr};
     const bool probe = g.restarts != nullptr;
-    return launch_triple<ModeSweepP, false>(g, m0, m1, g, 2, m2, p != nullptr, s, probe ? 0 : kVolOverlap,
-                                            probe ? -1 : kVolTail);
+    return launch_triple<ModeSweepP, false>(g, m0, m1, g, 2, m2, p != nullptr, s, probe ? 0 : kVolItems,
+                                            probe ? 0 : kVolOverlap, probe ? -1 : kVolTail);
 }
 
 hipError_t launch_drp_final(const Geo& g, int r, const float* z, float* znew, const float* q,
