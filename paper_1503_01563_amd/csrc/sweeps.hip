@@ -236,10 +236,13 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     const int lo = base;
     int hi = b1 + cfg.tail < m ? b1 + cfg.tail : m;
     const int slots = cfg.reach_lo + cfg.len + cfg.reach_hi;
-    // two spare rows per array: writes of lanes with nothing to emit, and
-    // values fetched from outside the window (row slots for L, slots + 1 for U)
-    float* lv = lds;                       // [slot][lane]: v, later segment value
-    float* la = lds + (slots + 2) * kPad;  // [slot][lane]: a, later edge dual
+    // [slot][lane] pairs (v, a), later (segment value, edge dual): one LDS
+    // access moves both.  Two spare rows: writes of lanes with nothing to
+    // emit, and values fetched from outside the window (row slots for L,
+    // slots + 1 for U).  Position q of this lane is at q * kPad + lb.
+    float2* lw = reinterpret_cast<float2*>(lds);
+    const int lb = lane - base * kPad;
+    const int spare = slots * kPad + lane;
 
     // Stage positions [qa, qb) of the 64 chains: B independent loads per lane
     // in flight before any LDS write (more for the initial window, when the
@@ -275,11 +278,7 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
                 }
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
-                    if (r2 < nrows) {
-                        const int sl = (qa + q2 - base) * kPad + r2;
-                        lv[sl] = vv[u];
-                        la[sl] = aa[u] + 0.f;
-                    }
+                    if (r2 < nrows) lw[(qa + q2 - base) * kPad + r2] = make_float2(vv[u], aa[u] + 0.f);
                     r2 += drr;
                     q2 += dq;
                     if (q2 >= len_r) {
@@ -301,10 +300,7 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
 #pragma unroll
                 for (int u = 0; u < B; ++u) {
                     const int q = qb0 + u;
-                    if (q < qb) {
-                        lv[(q - base) * kPad + lane] = vv[u];
-                        la[(q - base) * kPad + lane] = aa[u] + 0.f;
-                    }
+                    if (q < qb) lw[__mul24(q, kPad) + lb] = make_float2(vv[u], aa[u] + 0.f);
                 }
             }
         }
@@ -322,21 +318,19 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     // from global memory by the backward pass) and mark the knot in the
     // lane's bit masks.
     auto a_before = [&](int q) -> float {
-        return (q >= lo && q < hi) ? la[(q - base) * kPad + lane] : mode.a_at(ch.base + q * ch.stride);
+        return (q >= lo && q < hi) ? lw[__mul24(q, kPad) + lb].y : mode.a_at(ch.base + q * ch.stride);
     };
     constexpr int kGrow = 8;
     const int W0 = cfg.overlap > 0 ? cfg.overlap : 1;
     LeanLaneT<kExact> pl;
     pl.begin(valid, m, b0, b1, W0, a_before);
     auto mark = [&](int q, float cv, const LeanSeg& sg, bool on) {
-        const int sl = (on ? q - base : slots) * kPad + lane;
+        const int sl = on ? __mul24(q, kPad) + lb : spare;
         if constexpr (kExact) {
             const float chi = (float)sg.c;
-            lv[sl] = chi;
-            la[sl] = (float)(sg.c - (double)chi);
+            lw[sl] = make_float2(chi, (float)(sg.c - (double)chi));
         } else {
-            lv[sl] = cv;
-            la[sl] = -1.f;
+            lw[sl] = make_float2(cv, -1.f);
         }
     };
     auto grow = [&]() {
@@ -350,18 +344,16 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     // (rare: the deeper overlap after a failed bracket, a tail beyond the
     // reserve) is fetched from global memory into the lane's slot of the
     // spare row first, so that the read itself is always an LDS read.
-    const int spare = slots * kPad + lane;
     auto slot_of = [&](int q) {
         const bool in = (q >= lo) & (q < hi);
         if (__any(!in)) {
             if (!in) {
                 const int i = ch.base + q * ch.stride;
-                lv[spare] = mode.v_at(i);
-                la[spare] = mode.a_at(i);
+                lw[spare] = make_float2(mode.v_at(i), mode.a_at(i));
             }
             wave_fence();
         }
-        return in ? (q - base) * kPad + lane : spare;
+        return in ? __mul24(q, kPad) + lb : spare;
     };
     // While some lane brackets: both scans, U only where it brackets.
     // Positions outside the window go through the spare rows (L's in
@@ -376,30 +368,25 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
         if (__any(!inl || !inu)) {
             if (!inl) {
                 const int i = ch.base + ql * ch.stride;
-                lv[spare] = mode.v_at(i);
-                la[spare] = mode.a_at(i);
+                lw[spare] = make_float2(mode.v_at(i), mode.a_at(i));
             }
             if (!inu) {
                 const int i = ch.base + qu * ch.stride;
-                lv[spare_u] = mode.v_at(i);
-                la[spare_u] = mode.a_at(i);
+                lw[spare_u] = make_float2(mode.v_at(i), mode.a_at(i));
             }
             wave_fence();
         }
-        const int sl = inl ? (ql - base) * kPad + lane : spare;
-        const int su = inu ? (qu - base) * kPad + lane : spare_u;
-        const float vl = lv[sl], al = la[sl], vu = lv[su], au = la[su];
-        pl.step_l(gl, vl, ql + 1 < m ? al : 0.f, mark);
-        pl.step_u(gu, vu, qu + 1 < m ? au : 0.f);
+        const float2 xl = lw[inl ? __mul24(ql, kPad) + lb : spare], xu = lw[inu ? __mul24(qu, kPad) + lb : spare_u];
+        pl.step_l(gl, xl.x, ql != m - 1 ? xl.y : 0.f, mark);
+        pl.step_u(gu, xu.x, qu != m - 1 ? xu.y : 0.f);
         pl.resolve(a_before);
     }
     // then L alone in every lane until its piece is covered
     while (__any(pl.scanning)) {
         grow();
         const int ql = pl.scanning ? pl.L.k : lo;
-        const int sl = slot_of(ql);
-        const float vl = lv[sl], al = la[sl];
-        if (pl.scanning) pl.step_plain(vl, ql + 1 < m ? al : 0.f, mark);
+        const float2 x = lw[slot_of(ql)];
+        if (pl.scanning) pl.step_plain(x.x, ql != m - 1 ? x.y : 0.f, mark);
     }
     wave_fence();
     if (g.restarts) {
@@ -417,10 +404,10 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
         // the segment covering b1 - 1 is in registers
         float cur = pl.c_last;
         for (int q = b1 - 1; q >= b0; --q) {
-            const int sl = (q - base) * kPad + lane;
-            const float aq = la[sl], vq = lv[sl];
-            cur = aq < 0.f ? vq : cur;
-            lv[sl] = cur;
+            const int sl = __mul24(q, kPad) + lb;
+            const float2 x = lw[sl];
+            cur = x.y < 0.f ? x.x : cur;
+            lw[sl].x = cur;
         }
     } else if (valid) {
         // Backward from b1 - 1, where the covering segment's value and the
@@ -447,15 +434,15 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
             for (int u = 0; u < kB; ++u) {
                 const int q = qt - u;
                 if (q >= b0) {
-                    const int sl = (q - base) * kPad + lane;
-                    const float x0 = lv[sl], x1 = la[sl];
+                    const int sl = __mul24(q, kPad) + lb;
+                    const float2 x = lw[sl];
+                    const float x0 = x.x, x1 = x.y;
                     const bool kn = (pl.kmask >> (q - b0)) & 1ull;
                     const bool up = (pl.umask >> (q - b0)) & 1ull;
                     const float vq = kn ? gv[u] : x0, aq = kn ? ga[u] : x1;
                     cur = kn ? (double)x0 + (double)x1 : cur;
                     p = kn ? (double)(up ? aq : -aq) : p;
-                    lv[sl] = (float)cur;
-                    la[sl] = q == m - 1 ? 0.f : clip_dual(p, aq);
+                    lw[sl] = make_float2((float)cur, q == m - 1 ? 0.f : clip_dual(p, aq));
                     p += (double)vq - cur;
                 }
             }
@@ -471,8 +458,8 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
         int rr = lane / len_r, q = lane - rr * len_r;
         for (int t = 0; t * kLanes < total; ++t) {
             if (rr < nrows) {
-                const int sl = (b0 + q - base) * kPad + rr;
-                mode.store((c0 + rr) * g.W + b0 + q, lv[sl], kExact ? la[sl] : 0.f);
+                const float2 x = lw[(b0 + q - base) * kPad + rr];
+                mode.store((c0 + rr) * g.W + b0 + q, x.x, kExact ? x.y : 0.f);
             }
             rr += drr;
             q += dq;
@@ -487,8 +474,9 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 const int q = qb + u;
-                cv[u] = q < b1 ? lv[(q - base) * kPad + lane] : 0.f;
-                pv[u] = (kExact && q < b1) ? la[(q - base) * kPad + lane] : 0.f;
+                const float2 x = q < b1 ? lw[__mul24(q, kPad) + lb] : make_float2(0.f, 0.f);
+                cv[u] = x.x;
+                pv[u] = kExact ? x.y : 0.f;
             }
             typename M::Pre pre[kBatch];
 #pragma unroll
