@@ -42,7 +42,8 @@ struct PieceCfg {
 // about one wave per SIMD and get a longer overlap (12 instead of 8), so that
 // almost no piece has to restart its scans.  overlap > 0 sets the overlap
 // instead (the batched autotuner's candidates), tail >= 0 the tail.
-PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items, int overlap = 0, int tail = -1);
+PieceCfg piece_config(const Geo& g, int axis, int want, int launch_items, int overlap = 0, int tail = -1,
+                      int min_len = 16);
 constexpr int kDefaultItems = 4096;
 constexpr int kLatencyItems = 2048;
 // dynamic LDS bytes of a sweep launch with these pieces
