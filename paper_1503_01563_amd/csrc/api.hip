@@ -839,6 +839,7 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
     mc_opts o;
     if ((rc = read_opts(opts_in, o))) return rc;
     g.whole = (o.flags & MC_WHOLE_CHAINS) ? 1 : 0;
+    g.stream = (o.flags & MC_PIECE_CHAINS) ? 0 : 1;
     if ((o.flags & MC_FP64_STATE) &&
         (grid->conn == 8 || (o.variant != MC_VARIANT_AUTO && o.variant != MC_VARIANT_TWO_SET &&
                              o.variant != MC_VARIANT_PRODUCT)))
@@ -936,6 +937,7 @@ int mc_tv_solve_noalloc(mc_ctx* c, const mc_grid* grid, const float* w, const fl
     else return fail(MC_ERR_INVALID_ARG, "mc_tv_solve_noalloc: variant must be AUTO, TWO_SET or PRODUCT");
     if (two_set && g.ndim != 2) return fail(MC_ERR_INVALID_ARG, "two-set form needs a 2D grid");
     g.whole = (o.flags & MC_WHOLE_CHAINS) ? 1 : 0;
+    g.stream = (o.flags & MC_PIECE_CHAINS) ? 0 : 1;
     const size_t n = (size_t)g.n, r = (size_t)g.ndim;
     const size_t nz = two_set ? n : r * n;
     const size_t counts[5] = {nz, nz, two_set ? n : r * n, two_set ? 2 * n : r * n, n};  // z, z2, y, p, xt

@@ -15,6 +15,7 @@ struct Geo {
     int n;
     int ndim;
     int whole = 0;  // sweeps: every chain in one piece, one lane per chain (no overlap, no restarts)
+    int stream = 1;  // value sweeps of volumes may take streamed long pieces (0: short pieces only)
     int* restarts = nullptr;  // piece sweeps add {lanes that restarted, lanes run} here (null: no count)
 };
 

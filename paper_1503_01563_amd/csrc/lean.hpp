@@ -248,12 +248,15 @@ struct LeanLaneT {
     __host__ __device__ inline bool needs_u() const { return scanning && bracket && lastU <= lastL; }
 
     // L's step and what follows from it; br: the lane still brackets.
-    // mark(kend, c, seg, on) records a knot inside the piece (kend in
-    // [b0, b1 - 1)) once the bracket is resolved.
+    // mark(kend, c, seg, on, k0, out) records a knot inside the piece (on:
+    // kend in [b0, b1 - 1), once the bracket is resolved); out: a segment
+    // [k0, kend] of the result was finished (the streamed sweeps write every
+    // such segment).
     template <class Mark>
     __host__ __device__ inline void advance_l(bool br, float vk, float ak, const Mark& mark)
     {
         const int kp = L.k;
+        const int k0 = kp - (int)L.len;  // start of the open segment
         int kend;
         float c;
         LeanSeg sg;
@@ -269,7 +272,7 @@ struct LeanLaneT {
         ancL = fin & br ? L.nA : ancL;
         const bool out = fin & !br;
         const bool inside = out & (kend >= b0) & (kend < b1 - 1);
-        mark(kend, c, sg, inside);
+        mark(kend, c, sg, inside, k0, out);
         if constexpr (kExact) {
             const unsigned long long bit = inside ? 1ull << (kend - b0) : 0ull;
             kmask |= bit;

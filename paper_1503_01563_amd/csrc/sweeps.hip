@@ -324,7 +324,7 @@ __device__ __forceinline__ void sweep_piece(const Geo& g, int axis, int item, co
     const int W0 = cfg.overlap > 0 ? cfg.overlap : 1;
     LeanLaneT<kExact> pl;
     pl.begin(valid, m, b0, b1, W0, a_before);
-    auto mark = [&](int q, float cv, const LeanSeg& sg, bool on) {
+    auto mark = [&](int q, float cv, const LeanSeg& sg, bool on, int, bool) {
         const int sl = on ? __mul24(q, kPad) + lb : spare;
         if constexpr (kExact) {
             const float chi = (float)sg.c;
@@ -738,6 +738,276 @@ inline size_t lds_bytes(const PieceCfg& cfg)
 // 0.4 % later on (simulated on the volume's states).
 constexpr int kVolOverlap = 4, kVolTail = 0, kVolItems = 8192;
 
+// ---- long pieces streamed through an LDS ring (value sweeps of volumes) -----------
+//
+// The value sweeps of a volume after the first iterations: pieces of about
+// kStreamLen positions (a 256 x 256 x 128 volume: rows and columns in two
+// pieces, depth chains whole -- 3072 waves, 3 per SIMD, every wave about
+// 128 positions long), each scanned as the short pieces are (the lean scan,
+// bracketed from kVolOverlap positions before the piece unless it starts the
+// chain), but with the window streamed through a ring of kRing LDS rows
+// instead of staged whole: the overlap and the bracket are then paid once
+// per 128 positions instead of once per 16.  The ring holds positions
+// [lo, hi) of the 64 chains (row q mod kRing), staged kStage positions at a
+// time with coalesced loads issued one batch ahead.  A finished segment of
+// the result marks its last position with (value, -1); positions leave the
+// ring oldest first when the next batch needs the room: a backward pass gives
+// every position of the piece up to the lane's last finished one the value
+// of the next mark at or after it, and the batch goes to global memory with
+// coalesced stores, issued after the next batch is in.  A lane still reads
+// from the start of its open segment(s) on; while that is below the room
+// needed and some lane can still step, the lanes that reached hi wait.  Only
+// when every lane waits (a segment longer than kRing - kStage positions) the
+// oldest positions go anyway; a lane behind them reads them from global
+// memory through its spare slot, and writes the values of its finished
+// segments there directly.  Same results as the short pieces, bit for bit:
+// every piece is exact from a knot of the true solution or the chain start.
+constexpr int kRing = 16;      // positions per chain in the ring (a power of 2)
+constexpr int kStage = 8;      // positions staged at a time
+constexpr int kStreamLen = 128;
+// launches with fewer 64-chain waves keep the short pieces (too few lanes otherwise)
+constexpr int kStreamMinWaves = 2048;
+
+inline size_t stream_lds_bytes() { return sizeof(float2) * (kRing + 2) * kPad + sizeof(int) * kLanes; }
+
+struct StreamCfg {
+    int len, pieces;
+};
+
+inline StreamCfg stream_config(const Geo& g, int axis)
+{
+    const int m = geo_extent(g, axis);
+    int pieces = (m + kStreamLen / 2) / kStreamLen;
+    pieces = pieces < 1 ? 1 : pieces;
+    StreamCfg c;
+    c.len = (m + pieces - 1) / pieces;
+    c.pieces = (m + c.len - 1) / c.len;
+    return c;
+}
+
+template <bool kRows>
+__device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, int s, int len, const ModeSweepP& mode,
+                                             float2* ring, int* lastk_sh)
+{
+    const int lane = threadIdx.x;
+    const int nch = geo_nchains(g, axis);
+    const int m = geo_extent(g, axis);
+    const int c0 = grp * kLanes;
+    const bool valid = c0 + lane < nch;
+    const int nrows = nch - c0 < kLanes ? nch - c0 : kLanes;
+    const Chain ch = chain_of(g, axis, valid ? c0 + lane : c0);
+    const int b0 = s * len;
+    const int b1 = b0 + len < m ? b0 + len : m;
+    const int spare = kRing * kPad + lane, spare_u = spare + kPad;
+    auto slot = [&](int q, int r) { return __mul24(q & (kRing - 1), kPad) + r; };
+
+    // Prefetch registers: one batch of kStage positions of the 64 chains.
+    // Rows (chains along W, contiguous): element lane + 64 u of the
+    // 64 x kStage block is chain (lane + 64 u) / kStage, position
+    // (lane + 64 u) mod kStage, so that kStage consecutive lanes read one
+    // row's consecutive positions; otherwise position qa + u of the lane's
+    // chain.  Elements past the chain's end re-read its last position.
+    constexpr int kRowsPer = kLanes / kStage;
+    auto e_row = [&](int u) { return kRows ? lane / kStage + kRowsPer * u : lane; };
+    auto e_pos = [&](int qa, int u) { return kRows ? qa + lane % kStage : qa + u; };
+    auto gidx = [&](int r, int q) { return kRows ? (c0 + r) * g.W + q : ch.base + q * ch.stride; };
+    float pv[kStage], pa[kStage], ov[kStage];
+    auto issue = [&](int qa) {
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int r = e_row(u), q = e_pos(qa, u);
+            const int i = gidx(r < nrows ? r : nrows - 1, q < m ? q : m - 1);
+            pv[u] = mode.v_at(i);
+            pa[u] = mode.a_at(i);
+        }
+    };
+    auto commit = [&](int qa, int qb) {
+#pragma unroll
+        for (int u = 0; u < kStage; ++u) {
+            const int r = e_row(u), q = e_pos(qa, u);
+            if (r < nrows && q < qb) ring[slot(q, r)] = make_float2(pv[u], pa[u] + 0.f);
+        }
+    };
+
+    // the window starts at the weight in front of the bracket's start
+    int lo = b0 - kVolOverlap - 1 > 0 ? b0 - kVolOverlap - 1 : 0;
+    int hi = lo + kStage < m ? lo + kStage : m;
+    issue(lo);
+    commit(lo, hi);
+    if (hi < m) issue(hi);
+    wave_fence();
+
+    int lastk = -1;        // last position of the lane's last finished segment
+    int fq = 1, fe = 0;    // positions of a finished segment to write directly
+    float fc = 0.f;
+    auto a_before = [&](int q) -> float {
+        return (q >= lo && q < hi) ? ring[slot(q, lane)].y : mode.a_at(ch.base + q * ch.stride);
+    };
+    auto mark = [&](int q, float cv, const LeanSeg&, bool, int k0, bool out) {
+        ring[out && q >= lo ? slot(q, lane) : spare] = make_float2(cv, -1.f);
+        lastk = out ? q : lastk;
+        const int e0 = q < lo - 1 ? q : lo - 1;
+        fq = out ? (k0 > b0 ? k0 : b0) : 1;
+        fe = out ? (e0 < b1 - 1 ? e0 : b1 - 1) : 0;
+        fc = cv;
+    };
+    auto fill_direct = [&]() {
+        while (__any(fq <= fe)) {
+            if (fq <= fe) {
+                mode.store(ch.base + fq * ch.stride, fc, 0.f);
+                ++fq;
+            }
+        }
+        fq = 1;
+        fe = 0;
+    };
+    LeanLaneT<false> pl;
+    pl.begin(valid, m, b0, b1, kVolOverlap, a_before);
+
+    // Positions [qa, qb) of the piece leave the ring or are final: each
+    // lane's positions up to lastk take the value of the next mark at or
+    // after them (searched from top - 1 down), written over v in the ring.
+    auto fill_back = [&](int qa, int qb, int top) {
+        wave_fence();
+        float cur = 0.f;
+        for (int q = top - 1; q >= qa; --q) {
+            const int sl = slot(q, lane);
+            const float2 x = ring[sl];
+            cur = x.y < 0.f ? x.x : cur;
+            if (q < qb) ring[sl].x = cur;
+        }
+        lastk_sh[lane] = lastk;
+        wave_fence();
+    };
+    // oldest position a lane may still read: the start of its open segment
+    // (of both scans while it brackets)
+    auto need_of = [&]() {
+        int nd = pl.scanning ? pl.L.k - (int)pl.L.len : m;
+        const int nu = pl.U.k - (int)pl.U.len;
+        nd = pl.scanning && pl.bracket && nu < nd ? nu : nd;
+#pragma unroll
+        for (int o = kLanes / 2; o > 0; o >>= 1) {
+            const int t = __shfl_xor(nd, o);
+            nd = t < nd ? t : nd;
+        }
+        return nd;
+    };
+    // Stage the next batch when some lane needs position hi; evictions
+    // (at most kStage positions) read their values into registers before the
+    // batch overwrites their slots and store them after it is in.
+    auto stage = [&](bool want, bool can_step) {
+        if (hi >= m || !want) return;
+        const int nh = hi + kStage < m ? hi + kStage : m;
+        const int nl = nh - kRing > lo ? nh - kRing : lo;
+        if (nl > lo && nl > need_of() && can_step) return;  // the lanes at hi wait
+        const int ol = lo;
+        if (nl > ol) {
+            fill_back(ol, nl, hi);
+#pragma unroll
+            for (int u = 0; u < kStage; ++u) ov[u] = ring[slot(e_pos(ol, u), e_row(u))].x;
+            wave_fence();
+        }
+        commit(hi, nh);
+        if (nl > ol) {
+#pragma unroll
+            for (int u = 0; u < kStage; ++u) {
+                const int r = e_row(u), q = e_pos(ol, u);
+                if (r < nrows && q < nl && q >= b0 && q < b1 && q <= lastk_sh[r]) mode.store(gidx(r, q), ov[u], 0.f);
+            }
+        }
+        lo = nl;
+        hi = nh;
+        if (hi < m) issue(hi);
+        wave_fence();
+    };
+
+    // both scans while some lane brackets (positions below lo through the
+    // spare slots: L's in row kRing, U's in row kRing + 1)
+    while (__any(pl.bracket && pl.scanning)) {
+        const bool gl0 = pl.steps_l(), gu0 = pl.needs_u();
+        stage(__any((gl0 && pl.L.k >= hi) || (gu0 && pl.U.k >= hi)),
+              __any((gl0 && pl.L.k < hi) || (gu0 && pl.U.k < hi)));
+        const bool gl = gl0 && pl.L.k < hi, gu = gu0 && pl.U.k < hi;
+        const int ql = gl ? pl.L.k : lo, qu = gu ? pl.U.k : lo;
+        const bool inl = ql >= lo, inu = qu >= lo;
+        if (__any(!inl || !inu)) {
+            if (!inl) {
+                const int i = ch.base + ql * ch.stride;
+                ring[spare] = make_float2(mode.v_at(i), mode.a_at(i));
+            }
+            if (!inu) {
+                const int i = ch.base + qu * ch.stride;
+                ring[spare_u] = make_float2(mode.v_at(i), mode.a_at(i));
+            }
+            wave_fence();
+        }
+        const float2 xl = ring[inl ? slot(ql, lane) : spare], xu = ring[inu ? slot(qu, lane) : spare_u];
+        pl.step_l(gl, xl.x, ql != m - 1 ? xl.y : 0.f, mark);
+        pl.step_u(gu, xu.x, qu != m - 1 ? xu.y : 0.f);
+        pl.resolve(a_before);
+        fill_direct();
+    }
+    // then L alone in every lane until its piece is covered
+    while (__any(pl.scanning)) {
+        stage(__any(pl.scanning && pl.L.k >= hi), __any(pl.scanning && pl.L.k < hi));
+        const bool go = pl.scanning && pl.L.k < hi;
+        const int ql = go ? pl.L.k : lo;
+        const bool in = ql >= lo;
+        if (__any(!in)) {
+            if (!in) {
+                const int i = ch.base + ql * ch.stride;
+                ring[spare] = make_float2(mode.v_at(i), mode.a_at(i));
+            }
+            wave_fence();
+        }
+        const float2 x = ring[in ? slot(ql, lane) : spare];
+        if (go) pl.step_plain(x.x, ql != m - 1 ? x.y : 0.f, mark);
+        fill_direct();
+    }
+    // the rest of the piece: every lane is final up to b1 - 1
+    const int qa = lo > b0 ? lo : b0;
+    if (qa < b1) {
+        fill_back(qa, b1, hi);
+        const int len_r = b1 - qa;
+        if (kRows) {
+            const int total = nrows * len_r;
+            const int drr = kLanes / len_r, dq = kLanes - drr * len_r;
+            int rr = lane / len_r, q = lane - rr * len_r;
+            for (int t = 0; t * kLanes < total; ++t) {
+                if (rr < nrows) mode.store(gidx(rr, qa + q), ring[slot(qa + q, rr)].x, 0.f);
+                rr += drr;
+                q += dq;
+                if (q >= len_r) {
+                    q -= len_r;
+                    ++rr;
+                }
+            }
+        } else if (valid) {
+            for (int q = qa; q < b1; ++q) mode.store(gidx(lane, q), ring[slot(q, lane)].x, 0.f);
+        }
+    }
+}
+
+// the value sweep of the three families of a volume in streamed pieces (mode j
+// sweeps axis j): waves [0, w1) the columns, [w1, w1 + w0) the rows, the rest
+// the depth chains; wave -> (chain group, piece) with the piece fastest
+__global__ void __launch_bounds__(kLanes)
+k_stream3(Geo g, ModeSweepP m0, ModeSweepP m1, ModeSweepP m2, StreamCfg s0, StreamCfg s1, StreamCfg s2, int w1,
+          int w0)
+{
+    extern __shared__ __attribute__((aligned(16))) float lds[];
+    float2* ring = reinterpret_cast<float2*>(lds);
+    int* lastk_sh = reinterpret_cast<int*>(ring + (kRing + 2) * kPad);
+    const int b = blockIdx.x;
+    if (b < w1)
+        stream_piece<false>(g, 1, b / s1.pieces, b % s1.pieces, s1.len, m1, ring, lastk_sh);
+    else if (b < w1 + w0)
+        stream_piece<true>(g, 0, (b - w1) / s0.pieces, (b - w1) % s0.pieces, s0.len, m0, ring, lastk_sh);
+    else
+        stream_piece<false>(g, 2, (b - w1 - w0) / s2.pieces, (b - w1 - w0) % s2.pieces, s2.len, m2, ring, lastk_sh);
+}
+
+
 // the launch of k_sweep_triple with the latency / throughput mode decided on
 // its total number of work items; in throughput mode, want > 0 (work items
 // per family) and overlap / tail >= 0 replace the defaults
@@ -1113,6 +1383,16 @@ hipError_t launch_sweeps3(const Geo& g, const float* z, const float* const* a, f
     ModeSweepP m0{z, a[0], q, p};
     ModeSweepP m1{z + n, a[1], q + n, p ? p + n : nullptr};
     const bool probe = g.restarts != nullptr;
+    if (!p && !probe && g.stream) {  // value sweeps in streamed pieces when there are enough
+        const StreamCfg s0 = stream_config(g, 0), s1 = stream_config(g, 1), s2 = stream_config(g, 2);
+        auto waves = [&](int axis, const StreamCfg& c) { return (geo_nchains(g, axis) + kLanes - 1) / kLanes * c.pieces; };
+        const int w0 = waves(0, s0), w1 = waves(1, s1), w2 = waves(2, s2);
+        if (w0 + w1 + w2 >= kStreamMinWaves) {
+            hipLaunchKernelGGL(k_stream3, dim3(w0 + w1 + w2), dim3(kLanes), stream_lds_bytes(), s, g, m0, m1, m2, s0, s1,
+                               s2, w1, w0);
+            return hipGetLastError();
+        }
+    }
     return launch_triple<ModeSweepP, false>(g, m0, m1, g, 2, m2, p != nullptr, s, probe ? 0 : kVolItems,
                                             probe ? 0 : kVolOverlap, probe ? -1 : kVolTail);
 }
