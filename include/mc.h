@@ -150,6 +150,9 @@ typedef struct {
     int32_t checks;       /* certificate evaluations performed */
     int32_t items;        /* batched solves: work items per sweep launch used */
     int32_t whole_chains; /* mc_tv_solve splitting: 1 when the sweeps ended as whole chains */
+    double dual_sweep_ms;  /* MC_PROFILE: the part of sweep_ms spent in launches that also wrote edge
+                              duals (certificate iterations; mc_tv_solve splitting, else 0) */
+    int32_t dual_sweep_launches; /* how many of sweep_launches those were */
 } mc_stats;
 
 /* Fill `o` with the defaults listed above. */

@@ -119,10 +119,14 @@ struct SweepTimer {
     mc_ctx* c;
     bool on;
     size_t used = 0;
-    double ms = 0.0;
-    int launches = 0;
-    hipError_t begin(hipStream_t s)
+    double ms = 0.0, dual_ms = 0.0;
+    int launches = 0, dual_launches = 0;
+    bool cur_dual = false;
+    std::vector<uint8_t> tags;  // per timed launch: 1 when it also wrote edge duals
+    // dual: the launch also writes the edge duals (a certificate iteration)
+    hipError_t begin(hipStream_t s, bool dual = false)
     {
+        cur_dual = dual;
         if (!on) return hipSuccess;
         if (used + 2 > c->prof_ev.size()) {
             for (int k = 0; k < 2; ++k) {
@@ -137,9 +141,11 @@ struct SweepTimer {
     hipError_t end(hipStream_t s)
     {
         ++launches;
+        if (cur_dual) ++dual_launches;
         if (!on) return hipSuccess;
         hipError_t r = hipEventRecord(c->prof_ev[used + 1], s);
         used += 2;
+        tags.push_back(cur_dual ? 1 : 0);
         return r;
     }
     // call after the stream has been synchronised
@@ -150,8 +156,10 @@ struct SweepTimer {
             hipError_t r = hipEventElapsedTime(&t, c->prof_ev[k], c->prof_ev[k + 1]);
             if (r != hipSuccess) return r;
             ms += t;
+            if (tags[k / 2]) dual_ms += t;
         }
         used = 0;
+        tags.clear();
         return hipSuccess;
     }
 };
@@ -278,6 +286,8 @@ int finish_solve(mc_ctx* c, const SolveWs& ws, const Geo& g, const float* state,
     MC_HIP(tm.drain());
     stats->sweep_ms = tm.ms;
     stats->sweep_launches = tm.launches;
+    stats->dual_sweep_ms = tm.dual_ms;
+    stats->dual_sweep_launches = tm.dual_launches;
     stats->checks = st.checks;
     stats->items = 0;
     stats->whole_chains = g.whole;
@@ -652,30 +662,30 @@ int solve_split(mc_ctx* c, const SolveWs& ws, Geo g, bool two_set, const float* 
         if (two_set && cold_first) {
             MC_HIP(hipMemsetAsync(ws.y, 0, sizeof(float) * n, s));
             if (check) MC_HIP(hipMemsetAsync(ws.p, 0, sizeof(float) * n, s));
-            MC_HIP(tm.begin(s));
+            MC_HIP(tm.begin(s, check));
             MC_HIP(launch_dr2_cols(g, ws.y, zc, zn, w, a[1], check ? ws.p + n : nullptr, s));
             MC_HIP(tm.end(s));
         } else if (cold_first) {
             if (check) MC_HIP(hipMemsetAsync(ws.p, 0, sizeof(float) * (size_t)r * n, s));
             MC_HIP(launch_cold_product(g, r, w, zn, s));
         } else if (two_set) {
-            MC_HIP(tm.begin(s));
+            MC_HIP(tm.begin(s, check));
             MC_HIP(launch_dr2_rows(g, zc, a[0], ws.y, check ? ws.p : nullptr, s));
             MC_HIP(tm.end(s));
-            MC_HIP(tm.begin(s));
+            MC_HIP(tm.begin(s, check));
             MC_HIP(launch_dr2_cols(g, ws.y, zc, zn, w, a[1], check ? ws.p + n : nullptr, s));
             MC_HIP(tm.end(s));
         } else if (r == 3) {
             // all three families in one launch, then the averaging step
-            MC_HIP(tm.begin(s));
+            MC_HIP(tm.begin(s, check));
             MC_HIP(launch_sweeps3(g, zc, a, ws.y, check ? ws.p : nullptr, s));
             MC_HIP(tm.end(s));
             MC_HIP(launch_combine3(n, zc, ws.y, w, zn, s));
         } else {
-            MC_HIP(tm.begin(s));
+            MC_HIP(tm.begin(s, check));
             MC_HIP(launch_drp_sweeps(g, r - 1, zc, a, ws.y, check ? ws.p : nullptr, s));
             MC_HIP(tm.end(s));
-            MC_HIP(tm.begin(s));
+            MC_HIP(tm.begin(s, check));
             MC_HIP(launch_drp_final(g, r, zc, zn, ws.y, a[r - 1], w,
                                     check ? ws.p + (size_t)(r - 1) * n : nullptr, s));
             MC_HIP(tm.end(s));
@@ -894,6 +904,8 @@ int mc_tv_solve(mc_ctx* c, const mc_grid* grid, const float* w, const float* con
         stats->ms += s1.ms;
         stats->sweep_ms += s1.sweep_ms;
         stats->sweep_launches += s1.sweep_launches;
+        stats->dual_sweep_ms += s1.dual_sweep_ms;
+        stats->dual_sweep_launches += s1.dual_sweep_launches;
         stats->checks += s1.checks;
         return rc;
     }

@@ -64,7 +64,8 @@ class Stats(ctypes.Structure):
                 ("lower_bound", ctypes.c_double), ("tv_gap", ctypes.c_double),
                 ("tau_used", ctypes.c_float), ("ms", ctypes.c_float),
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
-                ("checks", ctypes.c_int32), ("items", ctypes.c_int32), ("whole_chains", ctypes.c_int32)]
+                ("checks", ctypes.c_int32), ("items", ctypes.c_int32), ("whole_chains", ctypes.c_int32),
+                ("dual_sweep_ms", ctypes.c_double), ("dual_sweep_launches", ctypes.c_int32)]
 
 
 class MLStats(ctypes.Structure):
@@ -210,6 +211,8 @@ class SolveResult:
     sweep_launches: int = 0
     checks: int = 0
     whole_chains: int = 0
+    dual_sweep_ms: float = 0.0
+    dual_sweep_launches: int = 0
 
     @property
     def converged(self):
@@ -290,7 +293,7 @@ def _solve(entry, w, a, z0, max_iters, check_every, gap_tol, variant, tau0, vali
     _check(rc, allow_not_converged=True)
     return SolveResult(labels, x, z, st.status, st.iters, st.cert_gap, st.energy,
                        st.lower_bound, st.tau_used, st.ms, st.tv_gap, st.sweep_ms,
-                       st.sweep_launches, st.checks, st.whole_chains)
+                       st.sweep_launches, st.checks, st.whole_chains, st.dual_sweep_ms, st.dual_sweep_launches)
 
 
 def tv_prox_chains(v: torch.Tensor, a_axis: torch.Tensor, axis: int, return_p=False,

@@ -79,3 +79,18 @@ def test_streamed_volume_matches_reference(dev):
     assert np.abs(x - ref["x"]).max() / max(1.0, np.abs(ref["x"]).max()) <= REL_TOL
     z = res.z.cpu().numpy().ravel()
     assert np.abs(z - ref["z"]).max() / max(1.0, np.abs(ref["z"]).max()) <= REL_TOL
+
+
+@pytest.mark.parametrize("shape", [(12, 40, 56), (96, 80)])
+def test_dual_sweep_time_is_reported(dev, shape):
+    """MC_PROFILE: the sweep time of the launches that also wrote edge duals
+    (the certificate iterations) is reported apart; their number follows the
+    check schedule (one launch per iteration in the product space, two in
+    the two-set form)."""
+    from paper_1503_01563_amd import mc
+    w, a = gen.iid_grid(shape, 1234)
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], max_iters=9, check_every=4, gap_tol=0.0, profile=True)
+    per_it = 1 if len(shape) == 3 else 2
+    assert res.checks == 3
+    assert res.dual_sweep_launches == 3 * per_it
+    assert 0.0 < res.dual_sweep_ms < res.sweep_ms

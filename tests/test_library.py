@@ -77,8 +77,9 @@ def test_struct_layouts_match_header():
     from paper_1503_01563_amd import mc
     assert ctypes.sizeof(mc.Grid) == 32
     assert ctypes.sizeof(mc.Opts) == 48
-    assert ctypes.sizeof(mc.Stats) == 72
+    assert ctypes.sizeof(mc.Stats) == 88
     assert mc.Stats.ms.offset == 44 and mc.Opts.flags.offset == 24
+    assert mc.Stats.dual_sweep_ms.offset == 72 and mc.Stats.dual_sweep_launches.offset == 80
     assert mc.Opts.batch_items.offset == 28 and mc.Opts.bcd_iters.offset == 32 and mc.Opts.reserved.offset == 36
     assert ctypes.sizeof(mc.MLStats) == 56
     assert (mc.MLStats.dr_iters.offset, mc.MLStats.energy0.offset, mc.MLStats.energy.offset,
