@@ -274,7 +274,7 @@ struct LeanLaneT {
         const bool inside = out & (kend >= b0) & (kend < b1 - 1);
         mark(kend, c, sg, inside, k0, out);
         if constexpr (kExact) {
-            const unsigned long long bit = inside ? 1ull << (kend - b0) : 0ull;
+            const unsigned long long bit = inside & (kend - b0 < 64) ? 1ull << (kend - b0) : 0ull;
             kmask |= bit;
             umask |= sg.an > 0.f ? bit : 0ull;
         }

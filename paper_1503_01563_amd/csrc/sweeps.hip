@@ -738,9 +738,9 @@ inline size_t lds_bytes(const PieceCfg& cfg)
 // 0.4 % later on (simulated on the volume's states).
 constexpr int kVolOverlap = 4, kVolTail = 0, kVolItems = 8192;
 
-// ---- long pieces streamed through an LDS ring (value sweeps of volumes) -----------
+// ---- long pieces streamed through an LDS ring (sweeps of volumes) -------------------
 //
-// The value sweeps of a volume after the first iterations: pieces of about
+// The sweeps of a volume after the first iteration: pieces of about
 // kStreamLen positions (a 256 x 256 x 128 volume: rows and columns in two
 // pieces, depth chains whole -- 3072 waves, 3 per SIMD, every wave about
 // 128 positions long), each scanned as the short pieces are (the lean scan,
@@ -754,16 +754,21 @@ constexpr int kVolOverlap = 4, kVolTail = 0, kVolItems = 8192;
 // ring oldest first when the next batch needs the room: a backward pass gives
 // every position of the piece up to the lane's last finished one the value
 // of the next mark at or after it, and the batch goes to global memory with
-// coalesced stores, issued after the next batch is in.  A lane still reads
-// from the start of its open segment(s) on; while that is below the room
-// needed and some lane can still step, the lanes that reached hi wait.  Only
-// when every lane waits (a segment longer than kRing - kStage positions) the
-// oldest positions go anyway; a lane behind them reads them from global
-// memory through its spare slot, and writes the values of its finished
-// segments there directly.  Same results as the short pieces, bit for bit:
-// every piece is exact from a knot of the true solution or the chain start.
+// coalesced stores, issued after the next batch is in.  Sweeps that also
+// write edge duals fill every finished segment at once instead: its
+// positions in order, the dual carried forward in FP64 from the one in front
+// of the segment (P_e = P_{e-1} + c - v_e, Sec. 3.2), exactly +-a at its
+// knot; the ring slots then hold (value, dual) and leave as they are.  A
+// lane still reads from the start of its open segment(s) on; while that is
+// below the room needed and some lane can still step, the lanes that reached
+// hi wait.  Only when every lane waits (a segment longer than kRing - kStage
+// positions) the oldest positions go anyway; a lane behind them reads them
+// from global memory through its spare slot, and writes the values (and
+// duals) of its finished segments there directly.  Same values as the short
+// pieces (every piece is exact from a knot of the true solution or the chain
+// start); the duals agree to the FP64 rounding of the carried sums.
 constexpr int kRing = 16;      // positions per chain in the ring (a power of 2)
-constexpr int kStage = 8;      // positions staged at a time
+constexpr int kStage = 8;      // positions staged at a time (4 with duals: fewer registers, 3 waves per SIMD)
 constexpr int kStreamLen = 128;
 // launches with fewer 64-chain waves keep the short pieces (too few lanes otherwise)
 constexpr int kStreamMinWaves = 2048;
@@ -785,10 +790,11 @@ inline StreamCfg stream_config(const Geo& g, int axis)
     return c;
 }
 
-template <bool kRows>
+template <bool kRows, bool kExact>
 __device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, int s, int len, const ModeSweepP& mode,
                                              float2* ring, int* lastk_sh)
 {
+    constexpr int kSt = kExact ? 4 : kStage;  // positions staged at a time
     const int lane = threadIdx.x;
     const int nch = geo_nchains(g, axis);
     const int m = geo_extent(g, axis);
@@ -801,20 +807,20 @@ __device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, in
     const int spare = kRing * kPad + lane, spare_u = spare + kPad;
     auto slot = [&](int q, int r) { return __mul24(q & (kRing - 1), kPad) + r; };
 
-    // Prefetch registers: one batch of kStage positions of the 64 chains.
+    // Prefetch registers: one batch of kSt positions of the 64 chains.
     // Rows (chains along W, contiguous): element lane + 64 u of the
-    // 64 x kStage block is chain (lane + 64 u) / kStage, position
-    // (lane + 64 u) mod kStage, so that kStage consecutive lanes read one
+    // 64 x kSt block is chain (lane + 64 u) / kSt, position
+    // (lane + 64 u) mod kSt, so that kSt consecutive lanes read one
     // row's consecutive positions; otherwise position qa + u of the lane's
     // chain.  Elements past the chain's end re-read its last position.
-    constexpr int kRowsPer = kLanes / kStage;
-    auto e_row = [&](int u) { return kRows ? lane / kStage + kRowsPer * u : lane; };
-    auto e_pos = [&](int qa, int u) { return kRows ? qa + lane % kStage : qa + u; };
+    constexpr int kRowsPer = kLanes / kSt;
+    auto e_row = [&](int u) { return kRows ? lane / kSt + kRowsPer * u : lane; };
+    auto e_pos = [&](int qa, int u) { return kRows ? qa + lane % kSt : qa + u; };
     auto gidx = [&](int r, int q) { return kRows ? (c0 + r) * g.W + q : ch.base + q * ch.stride; };
-    float pv[kStage], pa[kStage], ov[kStage];
+    float pv[kSt], pa[kSt], ov[kSt], op[kExact ? kSt : 1];
     auto issue = [&](int qa) {
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
+        for (int u = 0; u < kSt; ++u) {
             const int r = e_row(u), q = e_pos(qa, u);
             const int i = gidx(r < nrows ? r : nrows - 1, q < m ? q : m - 1);
             pv[u] = mode.v_at(i);
@@ -823,7 +829,7 @@ __device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, in
     };
     auto commit = [&](int qa, int qb) {
 #pragma unroll
-        for (int u = 0; u < kStage; ++u) {
+        for (int u = 0; u < kSt; ++u) {
             const int r = e_row(u), q = e_pos(qa, u);
             if (r < nrows && q < qb) ring[slot(q, r)] = make_float2(pv[u], pa[u] + 0.f);
         }
@@ -831,37 +837,75 @@ __device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, in
 
     // the window starts at the weight in front of the bracket's start
     int lo = b0 - kVolOverlap - 1 > 0 ? b0 - kVolOverlap - 1 : 0;
-    int hi = lo + kStage < m ? lo + kStage : m;
+    int hi = lo + kSt < m ? lo + kSt : m;
     issue(lo);
     commit(lo, hi);
     if (hi < m) issue(hi);
     wave_fence();
 
     int lastk = -1;        // last position of the lane's last finished segment
-    int fq = 1, fe = 0;    // positions of a finished segment to write directly
+    int fq = 1, fe = 0;    // positions of a finished segment to write directly (values) or to fill (duals)
     float fc = 0.f;
+    double fc64 = 0.0, fA = 0.0;  // duals: the segment's FP64 value and the dual in front of it
+    int fend = 0;
+    float fan = 0.f;
     auto a_before = [&](int q) -> float {
         return (q >= lo && q < hi) ? ring[slot(q, lane)].y : mode.a_at(ch.base + q * ch.stride);
     };
-    auto mark = [&](int q, float cv, const LeanSeg&, bool, int k0, bool out) {
-        ring[out && q >= lo ? slot(q, lane) : spare] = make_float2(cv, -1.f);
+    auto mark = [&](int q, float cv, const LeanSeg& sg, bool, int k0, bool out) {
         lastk = out ? q : lastk;
-        const int e0 = q < lo - 1 ? q : lo - 1;
-        fq = out ? (k0 > b0 ? k0 : b0) : 1;
-        fe = out ? (e0 < b1 - 1 ? e0 : b1 - 1) : 0;
-        fc = cv;
+        if constexpr (kExact) {
+            // the whole segment [k0, q] is filled forward after the step
+            fq = out ? k0 : 1;
+            fe = out ? (q < b1 - 1 ? q : b1 - 1) : 0;
+            fend = q;
+            fc64 = sg.c;
+            fA = -(double)sg.nA;
+            fan = sg.an;
+        } else {
+            ring[out && q >= lo ? slot(q, lane) : spare] = make_float2(cv, -1.f);
+            const int e0 = q < lo - 1 ? q : lo - 1;
+            fq = out ? (k0 > b0 ? k0 : b0) : 1;
+            fe = out ? (e0 < b1 - 1 ? e0 : b1 - 1) : 0;
+            fc = cv;
+        }
     };
+    // Values: the finished segment's positions that left the ring already.
+    // Duals: every position of the finished segment [k0, kend] in order, the
+    // dual carried forward in FP64 from the one in front of it
+    // (P_e = P_{e-1} + c - v_e, Sec. 3.2), exactly +-a at the knot and 0 at
+    // the chain's end; positions of the piece take (value, clipped dual) in
+    // their ring slot, or in global memory when they left the ring already.
     auto fill_direct = [&]() {
-        while (__any(fq <= fe)) {
-            if (fq <= fe) {
-                mode.store(ch.base + fq * ch.stride, fc, 0.f);
-                ++fq;
+        if constexpr (kExact) {
+            double P = fA;
+            const float cf = (float)fc64;
+            while (__any(fq <= fe)) {
+                if (fq <= fe) {
+                    const bool in = fq >= lo;
+                    const int i = ch.base + fq * ch.stride;
+                    const float2 x = in ? ring[slot(fq, lane)] : make_float2(mode.v_at(i), mode.a_at(i));
+                    P += fc64 - (double)x.x;
+                    if (fq >= b0) {
+                        const float pd = fq == m - 1 ? 0.f : clip_dual(fq == fend ? (double)fan : P, x.y);
+                        if (in) ring[slot(fq, lane)] = make_float2(cf, pd);
+                        else mode.store(i, cf, pd);
+                    }
+                    ++fq;
+                }
+            }
+        } else {
+            while (__any(fq <= fe)) {
+                if (fq <= fe) {
+                    mode.store(ch.base + fq * ch.stride, fc, 0.f);
+                    ++fq;
+                }
             }
         }
         fq = 1;
         fe = 0;
     };
-    LeanLaneT<false> pl;
+    LeanLaneT<kExact> pl;
     pl.begin(valid, m, b0, b1, kVolOverlap, a_before);
 
     // Positions [qa, qb) of the piece leave the ring or are final: each
@@ -893,26 +937,37 @@ __device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, in
         return nd;
     };
     // Stage the next batch when some lane needs position hi; evictions
-    // (at most kStage positions) read their values into registers before the
+    // (at most kSt positions) read their values into registers before the
     // batch overwrites their slots and store them after it is in.
     auto stage = [&](bool want, bool can_step) {
         if (hi >= m || !want) return;
-        const int nh = hi + kStage < m ? hi + kStage : m;
+        const int nh = hi + kSt < m ? hi + kSt : m;
         const int nl = nh - kRing > lo ? nh - kRing : lo;
         if (nl > lo && nl > need_of() && can_step) return;  // the lanes at hi wait
         const int ol = lo;
         if (nl > ol) {
-            fill_back(ol, nl, hi);
+            if constexpr (kExact) {
+                wave_fence();
+                lastk_sh[lane] = lastk;
+                wave_fence();
+            } else {
+                fill_back(ol, nl, hi);
+            }
 #pragma unroll
-            for (int u = 0; u < kStage; ++u) ov[u] = ring[slot(e_pos(ol, u), e_row(u))].x;
+            for (int u = 0; u < kSt; ++u) {
+                const float2 x = ring[slot(e_pos(ol, u), e_row(u))];
+                ov[u] = x.x;
+                if constexpr (kExact) op[u] = x.y;
+            }
             wave_fence();
         }
         commit(hi, nh);
         if (nl > ol) {
 #pragma unroll
-            for (int u = 0; u < kStage; ++u) {
+            for (int u = 0; u < kSt; ++u) {
                 const int r = e_row(u), q = e_pos(ol, u);
-                if (r < nrows && q < nl && q >= b0 && q < b1 && q <= lastk_sh[r]) mode.store(gidx(r, q), ov[u], 0.f);
+                if (r < nrows && q < nl && q >= b0 && q < b1 && q <= lastk_sh[r])
+                    mode.store(gidx(r, q), ov[u], kExact ? op[u] : 0.f);
             }
         }
         lo = nl;
@@ -967,14 +1022,18 @@ __device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, in
     // the rest of the piece: every lane is final up to b1 - 1
     const int qa = lo > b0 ? lo : b0;
     if (qa < b1) {
-        fill_back(qa, b1, hi);
+        if constexpr (kExact) wave_fence();
+        else fill_back(qa, b1, hi);
         const int len_r = b1 - qa;
         if (kRows) {
             const int total = nrows * len_r;
             const int drr = kLanes / len_r, dq = kLanes - drr * len_r;
             int rr = lane / len_r, q = lane - rr * len_r;
             for (int t = 0; t * kLanes < total; ++t) {
-                if (rr < nrows) mode.store(gidx(rr, qa + q), ring[slot(qa + q, rr)].x, 0.f);
+                if (rr < nrows) {
+                    const float2 x = ring[slot(qa + q, rr)];
+                    mode.store(gidx(rr, qa + q), x.x, kExact ? x.y : 0.f);
+                }
                 rr += drr;
                 q += dq;
                 if (q >= len_r) {
@@ -983,7 +1042,10 @@ __device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, in
                 }
             }
         } else if (valid) {
-            for (int q = qa; q < b1; ++q) mode.store(gidx(lane, q), ring[slot(q, lane)].x, 0.f);
+            for (int q = qa; q < b1; ++q) {
+                const float2 x = ring[slot(q, lane)];
+                mode.store(gidx(lane, q), x.x, kExact ? x.y : 0.f);
+            }
         }
     }
 }
@@ -991,7 +1053,8 @@ __device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, in
 // the value sweep of the three families of a volume in streamed pieces (mode j
 // sweeps axis j): waves [0, w1) the columns, [w1, w1 + w0) the rows, the rest
 // the depth chains; wave -> (chain group, piece) with the piece fastest
-__global__ void __launch_bounds__(kLanes)
+template <bool kExact>
+__global__ void __launch_bounds__(kLanes) __attribute__((amdgpu_waves_per_eu(3, 3)))
 k_stream3(Geo g, ModeSweepP m0, ModeSweepP m1, ModeSweepP m2, StreamCfg s0, StreamCfg s1, StreamCfg s2, int w1,
           int w0)
 {
@@ -1000,11 +1063,12 @@ k_stream3(Geo g, ModeSweepP m0, ModeSweepP m1, ModeSweepP m2, StreamCfg s0, Stre
     int* lastk_sh = reinterpret_cast<int*>(ring + (kRing + 2) * kPad);
     const int b = blockIdx.x;
     if (b < w1)
-        stream_piece<false>(g, 1, b / s1.pieces, b % s1.pieces, s1.len, m1, ring, lastk_sh);
+        stream_piece<false, kExact>(g, 1, b / s1.pieces, b % s1.pieces, s1.len, m1, ring, lastk_sh);
     else if (b < w1 + w0)
-        stream_piece<true>(g, 0, (b - w1) / s0.pieces, (b - w1) % s0.pieces, s0.len, m0, ring, lastk_sh);
+        stream_piece<true, kExact>(g, 0, (b - w1) / s0.pieces, (b - w1) % s0.pieces, s0.len, m0, ring, lastk_sh);
     else
-        stream_piece<false>(g, 2, (b - w1 - w0) / s2.pieces, (b - w1 - w0) % s2.pieces, s2.len, m2, ring, lastk_sh);
+        stream_piece<false, kExact>(g, 2, (b - w1 - w0) / s2.pieces, (b - w1 - w0) % s2.pieces, s2.len, m2, ring,
+                                    lastk_sh);
 }
 
 
@@ -1383,13 +1447,17 @@ hipError_t launch_sweeps3(const Geo& g, const float* z, const float* const* a, f
     ModeSweepP m0{z, a[0], q, p};
     ModeSweepP m1{z + n, a[1], q + n, p ? p + n : nullptr};
     const bool probe = g.restarts != nullptr;
-    if (!p && !probe && g.stream) {  // value sweeps in streamed pieces when there are enough
+    if (!probe && g.stream) {  // sweeps in streamed pieces when there are enough
         const StreamCfg s0 = stream_config(g, 0), s1 = stream_config(g, 1), s2 = stream_config(g, 2);
         auto waves = [&](int axis, const StreamCfg& c) { return (geo_nchains(g, axis) + kLanes - 1) / kLanes * c.pieces; };
         const int w0 = waves(0, s0), w1 = waves(1, s1), w2 = waves(2, s2);
         if (w0 + w1 + w2 >= kStreamMinWaves) {
-            hipLaunchKernelGGL(k_stream3, dim3(w0 + w1 + w2), dim3(kLanes), stream_lds_bytes(), s, g, m0, m1, m2, s0, s1,
-                               s2, w1, w0);
+            if (p)
+                hipLaunchKernelGGL(k_stream3<true>, dim3(w0 + w1 + w2), dim3(kLanes), stream_lds_bytes(), s, g, m0, m1,
+                                   m2, s0, s1, s2, w1, w0);
+            else
+                hipLaunchKernelGGL(k_stream3<false>, dim3(w0 + w1 + w2), dim3(kLanes), stream_lds_bytes(), s, g, m0, m1,
+                                   m2, s0, s1, s2, w1, w0);
             return hipGetLastError();
         }
     }

@@ -1,8 +1,10 @@
-"""Value sweeps of volumes in long pieces streamed through an LDS ring: the
-same iterates as the short pieces, bit for bit (both are the exact scan from
-a knot of the true solution or the chain start), on the bench volume, on an
-odd-sized volume with short segments, and on one with long constant segments
-(lanes that fall behind the ring, positions evicted before they are final)."""
+"""Sweeps of volumes in long pieces streamed through an LDS ring: the same
+iterates as the short pieces, bit for bit on the bench volume (both are the
+exact scan from a knot of the true solution or the chain start), and the
+same certificate; to FP32 rounding on odd-sized volumes with short segments,
+long constant segments (lanes that fall behind the ring, positions evicted
+before they are final) and one segment per chain, where the primal built
+from the streamed dual sweep's edge duals is compared too."""
 import numpy as np
 import pytest
 
@@ -40,6 +42,7 @@ def test_streamed_sweeps_equal_piece_sweeps(dev, iters):
     assert res.whole_chains == 0 and ref.whole_chains == 0
     assert bool((res.z == ref.z).all()), float((res.z - ref.z).abs().max())
     assert res.energy == ref.energy
+    assert abs(res.cert_gap - ref.cert_gap) <= 1e-6 * max(1.0, abs(ref.lower_bound))
 
 
 @pytest.mark.parametrize("shape,case", [((160, 200, 300), "iid"), ((160, 200, 300), "smooth"),
@@ -61,10 +64,14 @@ def test_streamed_volumes_match_piece_sweeps(dev, shape, case):
         w = np.full(shape, 0.75, np.float32)
         _, a = gen.ellipse_grid(shape, 997, lam=1.0)
     wt, at = T(w, dev), [T(x, dev) for x in a]
-    ref = mc.tv_solve(wt, at, max_iters=7, check_every=4, gap_tol=0.0, return_z=True, whole_chains=False)
-    res = mc.tv_solve(wt, at, max_iters=7, check_every=4, gap_tol=0.0, return_z=True)
+    ref = mc.tv_solve(wt, at, max_iters=7, check_every=4, gap_tol=0.0, return_x=True, return_z=True,
+                      whole_chains=False)
+    res = mc.tv_solve(wt, at, max_iters=7, check_every=4, gap_tol=0.0, return_x=True, return_z=True)
     scale = max(1.0, float(ref.z.abs().max()))
     assert float((res.z - ref.z).abs().max()) / scale <= 1e-5
+    # x is built from the edge duals of the last (streamed, dual) sweep
+    xs = max(1.0, float(ref.x.abs().max()))
+    assert float((res.x - ref.x).abs().max()) / xs <= 1e-5
 
 
 def test_streamed_volume_matches_reference(dev):
