@@ -292,8 +292,8 @@ def main():
         "certified": all(res.converged for res in results),
         "energy": last.energy,
         "roofline": roofline(last, n, VOL_BYTES_VALUE, VOL_BYTES_DUALS,
-                             "k_stream3 (value launches: rows, columns and depth chains of the volume in "
-                             "streamed pieces; the dual launches are k_sweep_triple)",
+                             "k_stream3<false> (value launches: rows, columns and depth chains of the volume "
+                             "in streamed pieces; the dual launches are k_stream3<true>)",
                              measured_traffic(TRAFFIC_PROFILE)),
     }
     if args.image:
