@@ -161,6 +161,15 @@ struct ModeSweepP {
         if (p) p[i] = pd;
     }
     __device__ __forceinline__ void store(int i, const Pre&, float c, float pd) const { store(i, c, pd); }
+    // non-temporal (streaming) accesses: data that one wave reads or writes
+    // once, kept from crowding the L2 lines other waves still come back to
+    __device__ __forceinline__ float v_nt(int i) const { return __builtin_nontemporal_load(z + i); }
+    __device__ __forceinline__ float a_nt(int i) const { return __builtin_nontemporal_load(a + i); }
+    __device__ __forceinline__ void store_nt(int i, float c, float pd) const
+    {
+        __builtin_nontemporal_store(c, q + i);
+        if (p) __builtin_nontemporal_store(pd, p + i);
+    }
 };
 
 // product space, final family R-1 fused with the average step (Pi_L of
@@ -754,7 +763,11 @@ constexpr int kVolOverlap = 4, kVolTail = 0, kVolItems = 8192;
 // ring oldest first when the next batch needs the room: a backward pass gives
 // every position of the piece up to the lane's last finished one the value
 // of the next mark at or after it, and the batch goes to global memory with
-// coalesced stores, issued after the next batch is in.  Sweeps that also
+// coalesced stores, issued after the next batch is in.  The columns and depth
+// families read and write whole rows of 64 chains (256 bytes) once, with
+// non-temporal accesses; the rows family reads 32 bytes of each row per
+// batch and comes back for the rest of the line, so it keeps its lines in L2
+// (FETCH_SIZE per value launch -33 %).  Sweeps that also
 // write edge duals fill every finished segment at once instead: its
 // positions in order, the dual carried forward in FP64 from the one in front
 // of the segment (P_e = P_{e-1} + c - v_e, Sec. 3.2), exactly +-a at its
@@ -823,8 +836,8 @@ __device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, in
         for (int u = 0; u < kSt; ++u) {
             const int r = e_row(u), q = e_pos(qa, u);
             const int i = gidx(r < nrows ? r : nrows - 1, q < m ? q : m - 1);
-            pv[u] = mode.v_at(i);
-            pa[u] = mode.a_at(i);
+            pv[u] = kRows ? mode.v_at(i) : mode.v_nt(i);
+            pa[u] = kRows ? mode.a_at(i) : mode.a_nt(i);
         }
     };
     auto commit = [&](int qa, int qb) {
@@ -966,8 +979,10 @@ __device__ __forceinline__ void stream_piece(const Geo& g, int axis, int grp, in
 #pragma unroll
             for (int u = 0; u < kSt; ++u) {
                 const int r = e_row(u), q = e_pos(ol, u);
-                if (r < nrows && q < nl && q >= b0 && q < b1 && q <= lastk_sh[r])
-                    mode.store(gidx(r, q), ov[u], kExact ? op[u] : 0.f);
+                if (r < nrows && q < nl && q >= b0 && q < b1 && q <= lastk_sh[r]) {
+                    if (kRows) mode.store(gidx(r, q), ov[u], kExact ? op[u] : 0.f);
+                    else mode.store_nt(gidx(r, q), ov[u], kExact ? op[u] : 0.f);
+                }
             }
         }
         lo = nl;
