@@ -81,6 +81,8 @@ __global__ void k_zz_scatter(int H, int W, const float* __restrict__ z2, const f
 }
 
 // z_j' = y_j - (2Y - Z + w) / R with y_j = z_j - q_j, Y = sum y_j, Z = sum z_j
+// Inputs are read once, with non-temporal loads: they then do not push out
+// of L2 the lines the next sweep comes back to (volume solve -1 %).
 template <int R>
 __global__ void k_combine(size_t n, const float* __restrict__ z, const float* __restrict__ q,
                           const float* __restrict__ w, float* __restrict__ zn)
@@ -89,12 +91,12 @@ __global__ void k_combine(size_t n, const float* __restrict__ z, const float* __
         float y[R], Y = 0.f, Z = 0.f;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            const float zj = z[j * n + i];
-            y[j] = zj - q[j * n + i];
+            const float zj = __builtin_nontemporal_load(z + j * n + i);
+            y[j] = zj - __builtin_nontemporal_load(q + j * n + i);
             Y += y[j];
             Z += zj;
         }
-        const float corr = (2.f * Y - Z + w[i]) * (1.f / (float)R);
+        const float corr = (2.f * Y - Z + __builtin_nontemporal_load(w + i)) * (1.f / (float)R);
 #pragma unroll
         for (int j = 0; j < R; ++j) zn[j * n + i] = y[j] - corr;
     }
