@@ -418,7 +418,7 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
     if (nz > (size_t)kMaxNodes) return fail(MC_ERR_INVALID_ARG, "8-connected grid too large (2(H-1)W > 2^31 - 2^24)");
     int rc;
     if ((rc = ensure_ws(c, n, R))) return rc;
-    const size_t need = R * n + 4 * nz;
+    const size_t need = 2 * n + 4 * nz;
     if (need > c->g8cap) {
         (void)hipFree(c->g8buf);
         c->g8buf = nullptr;
@@ -429,8 +429,8 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
         }
         c->g8cap = need;
     }
-    float* q = c->g8buf;  // R*n prox outputs
-    float* zzv = q + R * n;
+    float* q = c->g8buf;  // prox of rows and columns (2n)
+    float* zzv = q + 2 * n;
     float* zza = zzv + nz;
     float* zzx = zza + nz;
     float* zzp = zzx + nz;
@@ -461,6 +461,7 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
     bool converged = false;
     float* zc = c->z;
     float* zn = c->z2;
+    bool zz_current = false;  // zzv holds the zig-zag families of zc
     while (it < o.max_iters) {
         ++it;
         const bool check = (it % o.check_every == 0) || it == o.max_iters;
@@ -469,15 +470,16 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
             if (check) MC_HIP(hipMemsetAsync(c->p, 0, sizeof(float) * R * n, s));
             MC_HIP(launch_cold_product(g, R, w, zn, s));
         } else {
-            // gather the zig-zag chains, then sweep all four families together
-            MC_HIP(launch_zz_gather(H, W, zc + 2 * n, zc + 3 * n, a[2], a[3], zzv, zza, s));
+            // the zig-zag chains are gathered once (with their weights); from
+            // then on the averaging step writes them
+            if (!zz_current) MC_HIP(launch_zz_gather(H, W, zc + 2 * n, zc + 3 * n, a[2], a[3], zzv, zza, s));
             MC_HIP(tm.begin(s));
             MC_HIP(launch_sweeps8(g, zc, a, q, check ? c->p : nullptr, gz, zzv, zza, zzx, check ? zzp : nullptr,
                                   s));
             MC_HIP(tm.end(s));
-            MC_HIP(launch_zz_scatter(H, W, zc + 2 * n, zc + 3 * n, zzx, check ? zzp : nullptr, q + 2 * n,
-                                     q + 3 * n, c->p + 2 * n, c->p + 3 * n, s));
-            MC_HIP(launch_combine4(n, zc, q, w, zn, s));
+            MC_HIP(launch_combine8(H, W, zc, q, zzx, check ? zzp : nullptr, w, zn, zzv, c->p + 2 * n,
+                                   c->p + 3 * n, s));
+            zz_current = true;
         }
         float* zt = zc;
         zc = zn;

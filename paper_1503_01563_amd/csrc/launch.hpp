@@ -104,10 +104,13 @@ hipError_t launch_cold_product(const Geo& g, int r, const float* w, float* zn, h
 // z2 / z3, edge weights from the diagonal / anti-diagonal arrays).
 hipError_t launch_zz_gather(int H, int W, const float* z2, const float* z3, const float* add, const float* aad,
                             float* zv, float* za, hipStream_t s);
-// Back: q2 / q3 per vertex (identity off the family's paths); when zp is not
-// null, the diagonal and anti-diagonal duals per cell.
-hipError_t launch_zz_scatter(int H, int W, const float* z2, const float* z3, const float* zx, const float* zp,
-                             float* q2, float* q3, float* pdd, float* pad, hipStream_t s);
+// Averaging step over the four families, zn_j = y_j - (2Y - Z + w)/4: z holds
+// the four families per vertex, q01 the row and column prox, zx the zig-zag
+// prox as straightened chains (q_2, q_3 = z off the families' paths).  Writes
+// zn per vertex, zn of families 2 and 3 straightened into zv, and, when zp is
+// not null, the diagonal and anti-diagonal duals per cell into pdd / pad.
+hipError_t launch_combine8(int H, int W, const float* z, const float* q01, const float* zx, const float* zp,
+                           const float* w, float* zn, float* zv, float* pdd, float* pad, hipStream_t s);
 // ---- FP64 state (MC_FP64_STATE, fp64.hip): one lane per whole chain ----------
 // Duals (nullable) are written as FP32 clipped to their boxes.
 hipError_t launch_dr2_rows64(const Geo& g, const double* z, const float* a_x, double* q1, float* p1, hipStream_t s);
@@ -121,8 +124,6 @@ hipError_t launch_combine64(size_t n, int r, const double* z, const double* q, c
 hipError_t launch_f32_to_f64(size_t n, const float* x, double* y, hipStream_t s);
 hipError_t launch_f64_to_f32(size_t n, const double* x, float* y, hipStream_t s);
 
-// Product-space averaging over four families: zn_j = y_j - (2Y - Z + w)/4.
-hipError_t launch_combine4(size_t n, const float* z, const float* q, const float* w, float* zn, hipStream_t s);
 // z_j' = y_j - (2Y - Z + w) / 3 for a volume's three families
 hipError_t launch_combine3(size_t n, const float* z, const float* q, const float* w, float* zn, hipStream_t s);
 // Certificate, energy and input checks with the diagonal edges.

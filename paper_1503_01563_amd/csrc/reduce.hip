@@ -238,30 +238,47 @@ __device__ __forceinline__ int ladder_count(float x, const Taus& tz)
 }
 
 // Ladder accumulators: e[t] for the thresholds, e[kNumTau] the TV-gap term.
-// Written without branches: the predicated adds cost less than exec-mask
-// regions, which also keep the loads of the next edges from being issued early.
+// Most nodes lie below or above every threshold (count 0 or kNumTau) and most
+// edges join nodes of the same count: a node of count 0 adds to `all`, which
+// store() folds into every e[t], an edge of equal counts adds nothing, and
+// only the rest take the per-threshold adds, written without branches inside
+// a region a wave skips when none of its lanes needs it.
 struct Ladder {
     double e[kNumTau + 1];
+    double all;
 
     __device__ __forceinline__ Ladder()
     {
 #pragma unroll
         for (int t = 0; t <= kNumTau; ++t) e[t] = 0.0;
+        all = 0.0;
     }
     // a node with cnt = c is in S_t for t >= c
     __device__ __forceinline__ void node(int c, double wv)
     {
+        all += c == 0 ? wv : 0.0;
+        if (c > 0 && c < kNumTau) {
 #pragma unroll
-        for (int t = 0; t < kNumTau; ++t)
-            if (t >= c) e[t] += wv;
+            for (int t = 1; t < kNumTau; ++t)
+                if (t >= c) e[t] += wv;
+        }
     }
     // an edge between nodes of cnt cu and cv is cut for t in [min, max)
     __device__ __forceinline__ void edge(int cu, int cv, double av)
     {
         const int lo = cu < cv ? cu : cv, hi = cu < cv ? cv : cu;
+        if (lo < hi) {
 #pragma unroll
-        for (int t = 0; t < kNumTau; ++t)
-            if (t >= lo && t < hi) e[t] += av;
+            for (int t = 0; t < kNumTau; ++t)
+                if (t >= lo && t < hi) e[t] += av;
+        }
+    }
+    // the block's sums (threshold energies, then the TV-gap term) to out
+    __device__ __forceinline__ void store(double* out)
+    {
+#pragma unroll
+        for (int t = 0; t < kNumTau; ++t) e[t] += all;
+        block_reduce_store<kNumTau + 1>(e, out);
     }
 };
 
@@ -333,7 +350,7 @@ k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, P
             }
         }
     }
-    block_reduce_store<kNumTau + 1>(L.e, partials + (size_t)blockIdx.x * (kNumTau + 1));
+    L.store(partials + (size_t)blockIdx.x * (kNumTau + 1));
 }
 
 // ---- 8-connected 2D grids -------------------------------------------------------
@@ -403,7 +420,7 @@ k_cut_ladder8(Geo g, const float* __restrict__ xc, const float* __restrict__ w, 
             cut_edge(xu, ladder_count(xu, tz), (double)a.p[3][i], (double)p.p[3][i], tz, xc, i + 1, L);
         }
     }
-    block_reduce_store<kNumTau + 1>(L.e, partials + (size_t)blockIdx.x * (kNumTau + 1));
+    L.store(partials + (size_t)blockIdx.x * (kNumTau + 1));
 }
 
 __global__ void __launch_bounds__(kReduceThreads)
@@ -487,7 +504,7 @@ k_batch_cut(BatchLaunch b, Taus tz, double* __restrict__ partials)
     for (Walk k(t.g, ((int)blockIdx.x - t.blk0) * kReduceThreads + threadIdx.x, t.nblk * kReduceThreads); k.i < t.g.n;
          k.next(t.g))
         cut_voxel<2>(t.g, t.xc, t.w, a, p, tz, k.i, k.c, L);
-    block_reduce_store<kNumTau + 1>(L.e, partials + (size_t)blockIdx.x * kCertValues);
+    L.store(partials + (size_t)blockIdx.x * kCertValues);
 }
 
 // one block per grid: fixed-order sum of the grid's block partials, then the

@@ -60,6 +60,26 @@ def test_iterates_match_reference(dev, shape, iters):
     assert abs(res.lower_bound - ref["lower_bound"]) <= 1e-3 * max(1.0, abs(ref["lower_bound"]))
 
 
+@pytest.mark.parametrize("warm", [False, True])
+@pytest.mark.parametrize("shape", [(12, 17), (7, 40), (2, 9), (1, 6), (6, 1), (3, 3)])
+def test_state_matches_reference(dev, shape, warm):
+    """State of all four families after 7 iterations, from zero and from a
+    random z0.  The averaging step takes the zig-zag prox from the straightened
+    chains and writes the next state both per vertex and straightened; with H
+    odd or even, a boundary row lies on no path of one family (identity)."""
+    from paper_1503_01563_amd import mc
+    w, a = problem(shape, 19)
+    z0 = np.random.default_rng(20).normal(0.0, 3.0, size=(4,) + shape).astype(np.float32) if warm else None
+    res = mc.tv_solve(T(w, dev), [T(x, dev) for x in a], z0=T(z0, dev).reshape(-1) if warm else None,
+                      max_iters=7, check_every=3, gap_tol=0.0, return_z=True)
+    ref = grid8.dr_solve(w, a, max_iters=7, gap_tol=0.0, check_every=3, z0=z0)
+    assert res.iters == ref["iters"] == 7
+    z = res.z.cpu().numpy().reshape(4, -1)
+    scale = max(1.0, np.abs(ref["z"]).max())
+    assert np.abs(z - ref["z"]).max() / scale <= REL_TOL
+    assert np.abs(res.x.cpu().numpy() - ref["x"]).max() / max(1.0, np.abs(ref["x"]).max()) <= REL_TOL
+
+
 @pytest.mark.parametrize("shape,seed", [((24, 31), 14), ((64, 64), 15), ((3, 50), 16), ((50, 3), 17)])
 def test_solve_exact_against_maxflow(dev, shape, seed):
     from paper_1503_01563_amd import mc
