@@ -168,6 +168,11 @@ __device__ __forceinline__ double primal_voxel(const Geo& g, const float* __rest
 // would otherwise hold back the next voxel's loads), then the voxels are
 // finished in walk order, so the sums are the same as voxel by voxel.
 constexpr int kGroup = 4;
+// The ladder holds eleven FP64 sums per lane: groups of two voxels keep it at
+// 64 VGPRs, eight waves per SIMD, so that all kReduceBlocks blocks of a
+// full-chip launch are resident at once (with groups of four, 86 VGPRs, five
+// waves: the launch ran in two rounds; 256x256x128 volume 74.6 -> 71.0 us).
+constexpr int kLadderGroup = 2;
 
 template <int ND>
 __global__ void __launch_bounds__(kReduceThreads)
@@ -316,11 +321,11 @@ k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, P
     Ladder L;
     Walk k(g);
     while (k.i < g.n) {
-        // loads of a group first (see kGroup), then the voxels in walk order
-        bool ok[kGroup], he[kGroup][ND];
-        float xi[kGroup], wv[kGroup], xn[kGroup][ND], av[kGroup][ND], pv[kGroup][ND];
+        // loads of a group first (see kLadderGroup), then the voxels in walk order
+        bool ok[kLadderGroup], he[kLadderGroup][ND];
+        float xi[kLadderGroup], wv[kLadderGroup], xn[kLadderGroup][ND], av[kLadderGroup][ND], pv[kLadderGroup][ND];
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
+        for (int u = 0; u < kLadderGroup; ++u) {
             ok[u] = k.i < g.n;
             const int i = ok[u] ? k.i : 0;
             const int cc[3] = {k.c.x, k.c.y, k.c.d};
@@ -336,7 +341,7 @@ k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, P
             k.next(g);
         }
 #pragma unroll
-        for (int u = 0; u < kGroup; ++u) {
+        for (int u = 0; u < kLadderGroup; ++u) {
             if (!ok[u]) continue;
             const int ci = ladder_count(xi[u], tz);
             L.node(ci, (double)wv[u]);
