@@ -206,19 +206,27 @@ struct CheckState {
     double cert = INFINITY, energy = INFINITY, lb = -INFINITY, tvgap = NAN;
     float tau_used = 0.f;
     int checks = 0;
+    bool ev1_recorded = false;  // ev1 marks the end of the last check
 };
 
 // Certificate from the edge duals pj (Sec. 2.2): energies of the threshold
-// ladder, LB, TV gap; `done` when cert < gap_tol.  Synchronises the stream.
-int run_check(mc_ctx* c, const SolveWs& ws, const Geo& g, bool conn8, const float* w, const float* const* a,
-              const float* const* pj, const mc_opts& o, const float* taus, SweepTimer& tm, hipStream_t s,
-              CheckState& st, bool& done)
+// ladder, LB, TV gap, copied to the host; ev1 is recorded behind the copy.
+int enqueue_check(mc_ctx* c, const SolveWs& ws, const Geo& g, bool conn8, const float* w, const float* const* a,
+                  const float* const* pj, const mc_opts& o, hipStream_t s, CheckState& st)
 {
     ++st.checks;
     if (conn8) MC_HIP(launch_cert8(g, w, a, pj, o.tau0, ws.xt, ws.partials, ws.dout, s));
     else MC_HIP(launch_cert(g, w, a, pj, o.tau0, ws.xt, ws.partials, ws.dout, s));
     MC_HIP(hipMemcpyAsync(c->hout, ws.dout, kCertValues * sizeof(double), hipMemcpyDeviceToHost, s));
-    MC_HIP(hipStreamSynchronize(s));
+    MC_HIP(hipEventRecord(c->ev1, s));
+    st.ev1_recorded = true;
+    return MC_OK;
+}
+
+// Waits for the last enqueued check and reads it; `done` when cert < gap_tol.
+int read_check(mc_ctx* c, const mc_opts& o, const float* taus, SweepTimer& tm, CheckState& st, bool& done)
+{
+    MC_HIP(hipEventSynchronize(c->ev1));
     MC_HIP(tm.drain());
     st.energy = INFINITY;
     for (int k = 0; k < kNumTau; ++k) {
@@ -233,6 +241,16 @@ int run_check(mc_ctx* c, const SolveWs& ws, const Geo& g, bool conn8, const floa
     if (!isfinite(st.cert)) return fail(MC_ERR_NUMERIC, "non-finite certificate (NaN/Inf in the state)");
     done = st.cert < o.gap_tol;
     return MC_OK;
+}
+
+// A check read at once.
+int run_check(mc_ctx* c, const SolveWs& ws, const Geo& g, bool conn8, const float* w, const float* const* a,
+              const float* const* pj, const mc_opts& o, const float* taus, SweepTimer& tm, hipStream_t s,
+              CheckState& st, bool& done)
+{
+    int rc;
+    if ((rc = enqueue_check(c, ws, g, conn8, w, a, pj, o, s, st))) return rc;
+    return read_check(c, o, taus, tm, st, done);
 }
 
 // MC_DEBUG: the state after iteration `it` holds no NaN/Inf.
@@ -268,7 +286,7 @@ int finish_solve(mc_ctx* c, const SolveWs& ws, const Geo& g, const float* state,
                  SweepTimer& tm, hipStream_t s)
 {
     const size_t n = (size_t)g.n;
-    MC_HIP(hipEventRecord(c->ev1, s));
+    if (!st.ev1_recorded) MC_HIP(hipEventRecord(c->ev1, s));
     MC_HIP(launch_labels(g, ws.xt, st.tau_used, labels_out, s));
     if (x_out) MC_HIP(hipMemcpyAsync(x_out, ws.xt, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
     if (z_out) MC_HIP(hipMemcpyAsync(z_out, state, sizeof(float) * nstate, hipMemcpyDeviceToDevice, s));
@@ -462,9 +480,13 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
     float* zc = c->z;
     float* zn = c->z2;
     bool zz_current = false;  // zzv holds the zig-zag families of zc
+    // checks are read behind the next iteration, as in solve_split
+    const bool overlap_checks = !(o.flags & MC_PROFILE);
+    bool pending = false;
+    auto is_check = [&](int i) { return (i % o.check_every == 0) || i == o.max_iters; };
     while (it < o.max_iters) {
         ++it;
-        const bool check = (it % o.check_every == 0) || it == o.max_iters;
+        const bool check = is_check(it);
         if (it == 1 && !z0) {
             // every prox of the zero state is zero (see mc_tv_solve)
             if (check) MC_HIP(hipMemsetAsync(c->p, 0, sizeof(float) * R * n, s));
@@ -484,9 +506,25 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
         float* zt = zc;
         zc = zn;
         zn = zt;
+        if (pending) {
+            pending = false;
+            bool done = false;
+            if ((rc = read_check(c, o, taus, tm, st, done))) return rc;
+            if (done) {  // certified at the previous iteration, whose state is in zn
+                converged = true;
+                --it;
+                zc = zn;
+                break;
+            }
+        }
         if (!check) continue;
+        if ((rc = enqueue_check(c, ctx_ws(c), g, true, w, a, pj, o, s, st))) return rc;
+        if (overlap_checks && it < o.max_iters && !is_check(it + 1)) {
+            pending = true;
+            continue;
+        }
         bool done = false;
-        if ((rc = run_check(c, ctx_ws(c), g, true, w, a, pj, o, taus, tm, s, st, done))) return rc;
+        if ((rc = read_check(c, o, taus, tm, st, done))) return rc;
         if (done) {
             converged = true;
             break;
@@ -653,9 +691,17 @@ int solve_split(mc_ctx* c, const SolveWs& ws, Geo g, bool two_set, const float* 
     if ((rc = probe.start())) return rc;
     float* zc = ws.z;   // current state
     float* zn = ws.z2;  // next state
+    // A check is read only once the next iteration is queued behind it (when
+    // that one is no check), so that the device does not idle while the host
+    // reads the result.  The extra iteration writes neither the duals nor the
+    // primal, and the state it leaves in the other buffer is that of the
+    // check, so a certified check still ends the solve with its own state.
+    const bool overlap_checks = !(o.flags & (MC_PROFILE | MC_DEBUG));
+    bool pending = false;
+    auto is_check = [&](int i) { return (i % o.check_every == 0) || i == o.max_iters; };
     while (it < o.max_iters) {
         ++it;
-        const bool check = (it % o.check_every == 0) || it == o.max_iters;
+        const bool check = is_check(it);
         // A cold start begins at z = 0, whose chain proxes are 0 with zero
         // duals (the prox of a constant chain is the chain itself).  Sweeping
         // that is slow -- every chain is one segment, so no bracket closes
@@ -697,10 +743,26 @@ int solve_split(mc_ctx* c, const SolveWs& ws, Geo g, bool two_set, const float* 
         zn = zt;
         if ((rc = probe.after_iteration(tm.launches))) return rc;
         if ((o.flags & MC_DEBUG) && (rc = debug_state(c, ws, zc, nz, it, s))) return rc;
+        if (pending) {
+            pending = false;
+            bool done = false;
+            if ((rc = read_check(c, o, taus, tm, st, done))) return rc;
+            if (done) {  // certified at the previous iteration, whose state is in zn
+                converged = true;
+                --it;
+                zc = zn;
+                break;
+            }
+        }
         if (!check) continue;
         if ((o.flags & MC_DEBUG) && (rc = debug_duals(c, ws, g, a, pj, it, s))) return rc;
+        if ((rc = enqueue_check(c, ws, g, false, w, a, pj, o, s, st))) return rc;
+        if (overlap_checks && it < o.max_iters && !is_check(it + 1)) {
+            pending = true;
+            continue;
+        }
         bool done = false;
-        if ((rc = run_check(c, ws, g, false, w, a, pj, o, taus, tm, s, st, done))) return rc;
+        if ((rc = read_check(c, o, taus, tm, st, done))) return rc;
         if (done) {
             converged = true;
             break;

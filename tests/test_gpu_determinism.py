@@ -50,3 +50,47 @@ def test_repeated_alpha_expansion_is_identical(dev):
         res = mc.alpha_expansion(T(data, dev), [T(x, dev) for x in lam], labels, 1, 2.0)
         outs.append((labels.cpu().numpy(), res.energy, res.dr_iters, res.accepted))
     assert np.array_equal(outs[0][0], outs[1][0]) and outs[0][1:] == outs[1][1:]
+
+
+@pytest.mark.parametrize("case,check_every,max_iters", [
+    ("image2d", 4, 3000), ("image2d", 3, 3000), ("image2d", 1, 3000), ("image2d", 4, 10),
+    ("product2d", 4, 3000), ("volume3d", 4, 3000), ("volume3d", 5, 13), ("warm2d", 2, 3000)])
+def test_overlapped_checks_match_checks_read_at_once(dev, case, check_every, max_iters):
+    """A check is read while the next iteration already runs (the default);
+    with MC_PROFILE every check is read at once.  Both end on the same
+    certified iteration with the same primal, labels, state and statistics,
+    also when max_iters stops the solve."""
+    from paper_1503_01563_amd import mc
+    if case == "volume3d":
+        w, a = gen.ellipse_grid((24, 48, 64), 3301, lam=1.5)
+    else:
+        w, a = gen.config_image2d(2005, (256, 320))
+    kw = {"variant": mc.VARIANT_PRODUCT} if case == "product2d" else {}
+    wt, at = T(w, dev), [T(x, dev) for x in a]
+    if case == "warm2d":
+        kw["z0"] = mc.tv_solve(wt, at, max_iters=12, check_every=12, gap_tol=0.0, return_z=True).z
+    runs = [mc.tv_solve(wt, at, max_iters=max_iters, check_every=check_every, return_z=True, profile=prof, **kw)
+            for prof in (False, True)]
+    r, ref = runs
+    assert ref.converged or max_iters < 3000
+    assert (r.iters, r.converged, r.checks, r.energy, r.cert_gap, r.lower_bound, r.tv_gap) == \
+        (ref.iters, ref.converged, ref.checks, ref.energy, ref.cert_gap, ref.lower_bound, ref.tv_gap)
+    assert np.array_equal(r.x.cpu().numpy().view(np.uint32), ref.x.cpu().numpy().view(np.uint32))
+    assert np.array_equal(r.labels.cpu().numpy(), ref.labels.cpu().numpy())
+    assert np.array_equal(r.z.cpu().numpy().view(np.uint32), ref.z.cpu().numpy().view(np.uint32))
+    assert r.ms > 0
+
+
+@pytest.mark.parametrize("check_every,max_iters", [(4, 3000), (3, 11)])
+def test_overlapped_checks_match_8connected(dev, check_every, max_iters):
+    from paper_1503_01563_amd import mc
+    w, a = gen.ellipse_grid8((96, 128), 3302)
+    wt, at = T(w, dev), [T(x, dev) for x in a]
+    r, ref = [mc.tv_solve(wt, at, max_iters=max_iters, check_every=check_every, return_z=True, profile=prof)
+              for prof in (False, True)]
+    assert ref.converged or max_iters < 3000
+    assert (r.iters, r.converged, r.checks, r.energy, r.cert_gap, r.lower_bound) == \
+        (ref.iters, ref.converged, ref.checks, ref.energy, ref.cert_gap, ref.lower_bound)
+    assert np.array_equal(r.x.cpu().numpy().view(np.uint32), ref.x.cpu().numpy().view(np.uint32))
+    assert np.array_equal(r.labels.cpu().numpy(), ref.labels.cpu().numpy())
+    assert np.array_equal(r.z.cpu().numpy().view(np.uint32), ref.z.cpu().numpy().view(np.uint32))
