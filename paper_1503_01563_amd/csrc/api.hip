@@ -484,6 +484,9 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
     const bool overlap_checks = !(o.flags & MC_PROFILE);
     bool pending = false;
     auto is_check = [&](int i) { return (i % o.check_every == 0) || i == o.max_iters; };
+    auto overlap = [&](int i) {
+        return overlap_checks && !g.whole && st.checks >= 3 && i < o.max_iters && !is_check(i + 1);
+    };
     while (it < o.max_iters) {
         ++it;
         const bool check = is_check(it);
@@ -519,7 +522,7 @@ int solve8(mc_ctx* c, const Geo& g, const float* w, const float* const* a, const
         }
         if (!check) continue;
         if ((rc = enqueue_check(c, ctx_ws(c), g, true, w, a, pj, o, s, st))) return rc;
-        if (overlap_checks && it < o.max_iters && !is_check(it + 1)) {
+        if (overlap(it)) {
             pending = true;
             continue;
         }
@@ -696,9 +699,16 @@ int solve_split(mc_ctx* c, const SolveWs& ws, Geo g, bool two_set, const float* 
     // reads the result.  The extra iteration writes neither the duals nor the
     // primal, and the state it leaves in the other buffer is that of the
     // check, so a certified check still ends the solve with its own state.
-    const bool overlap_checks = !(o.flags & (MC_PROFILE | MC_DEBUG));
-    bool pending = false;
+    // The iteration queued behind the certified check is lost time, so the
+    // first two checks of a solve are read at once (short solves, such as
+    // the moves of alpha-expansion, pay nothing), and whole-chain sweeps,
+    // whose iterations are long against the wait, never overlap.
     auto is_check = [&](int i) { return (i % o.check_every == 0) || i == o.max_iters; };
+    const bool overlap_checks = !(o.flags & (MC_PROFILE | MC_DEBUG));
+    auto overlap = [&](int i) {
+        return overlap_checks && !g.whole && st.checks >= 3 && i < o.max_iters && !is_check(i + 1);
+    };
+    bool pending = false;
     while (it < o.max_iters) {
         ++it;
         const bool check = is_check(it);
@@ -757,7 +767,7 @@ int solve_split(mc_ctx* c, const SolveWs& ws, Geo g, bool two_set, const float* 
         if (!check) continue;
         if ((o.flags & MC_DEBUG) && (rc = debug_duals(c, ws, g, a, pj, it, s))) return rc;
         if ((rc = enqueue_check(c, ws, g, false, w, a, pj, o, s, st))) return rc;
-        if (overlap_checks && it < o.max_iters && !is_check(it + 1)) {
+        if (overlap(it)) {
             pending = true;
             continue;
         }

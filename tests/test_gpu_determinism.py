@@ -53,13 +53,13 @@ def test_repeated_alpha_expansion_is_identical(dev):
 
 
 @pytest.mark.parametrize("case,check_every,max_iters", [
-    ("image2d", 4, 3000), ("image2d", 3, 3000), ("image2d", 1, 3000), ("image2d", 4, 10),
-    ("product2d", 4, 3000), ("volume3d", 4, 3000), ("volume3d", 5, 13), ("warm2d", 2, 3000)])
+    ("image2d", 4, 3000), ("image2d", 3, 3000), ("image2d", 1, 3000), ("image2d", 2, 15),
+    ("product2d", 4, 3000), ("volume3d", 4, 3000), ("volume3d", 2, 11), ("warm2d", 2, 3000)])
 def test_overlapped_checks_match_checks_read_at_once(dev, case, check_every, max_iters):
-    """A check is read while the next iteration already runs (the default);
-    with MC_PROFILE every check is read at once.  Both end on the same
-    certified iteration with the same primal, labels, state and statistics,
-    also when max_iters stops the solve."""
+    """From a solve's third check on, a check is read while the next
+    iteration already runs (the default); with MC_PROFILE every check is read
+    at once.  Both end on the same certified iteration with the same primal,
+    labels, state and statistics, also when max_iters stops the solve."""
     from paper_1503_01563_amd import mc
     if case == "volume3d":
         w, a = gen.ellipse_grid((24, 48, 64), 3301, lam=1.5)
