@@ -109,7 +109,7 @@ struct Ptr3 {
 // division per thread at the start, then at most one carry per axis per step
 // (x + sx < 2W and y + sy + 1 < 2H since both parts of the stride are reduced).
 struct Walk {
-    int i, stride;
+    int i, stride, end;
     Coords c;
     int sx, sy, sd;
 
@@ -120,6 +120,7 @@ struct Walk {
     __device__ __forceinline__ Walk(const Geo& g, int start, int step)
     {
         stride = step;
+        end = g.n;
         i = start;
         c = coords_of(g, i < g.n ? i : 0);
         const Coords s = coords_of(g, stride);
@@ -139,6 +140,26 @@ struct Walk {
         c.d += sd + cy;
     }
 };
+
+// Workgroups are dealt to the eight XCDs in turn (workgroup b runs on XCD
+// b mod 8), each with its own L2.  With one walk over the whole grid the
+// voxels one row away belong to workgroups on other XCDs, and a kernel that
+// reads them fetches those lines from memory again (the certificate kernels:
+// 1.2-1.3x their algorithmic bytes).  Here XCD x's workgroups walk together
+// through their own contiguous eighth of the grid, so a round of them covers
+// consecutive rows and the rows and slices next to it are in the same L2.
+// The launch takes a multiple of 8 workgroups.
+constexpr int kXcds = 8;
+
+__device__ __forceinline__ Walk xcd_walk(const Geo& g)
+{
+    const int x = (int)blockIdx.x % kXcds;
+    const int n8 = (g.n + kXcds - 1) / kXcds;
+    Walk k(g, x * n8 + ((int)blockIdx.x / kXcds) * kReduceThreads + (int)threadIdx.x,
+           ((int)gridDim.x / kXcds) * kReduceThreads);
+    k.end = (x + 1) * n8 < g.n ? (x + 1) * n8 : g.n;
+    return k;
+}
 
 // Primal estimate and lower bound from the edge duals (Sec. 2.2, 2.3):
 // y = sum_j D_j^T p_j with p clipped to its box (so y lies in K exactly),
@@ -181,15 +202,15 @@ k_primal(Geo g, const float* __restrict__ w, Ptr3 p, float* __restrict__ xc,
 {
     const int st[3] = {1, g.W, g.W * g.H};
     double lb = 0.0;
-    Walk k(g);
-    while (k.i < g.n) {
+    Walk k = xcd_walk(g);
+    while (k.i < k.end) {
         int idx[kGroup];
         bool ok[kGroup];
         float pc[kGroup][ND], pb[kGroup][ND], wv[kGroup];
         bool hb[kGroup][ND];
 #pragma unroll
         for (int u = 0; u < kGroup; ++u) {
-            ok[u] = k.i < g.n;
+            ok[u] = k.i < k.end;
             idx[u] = ok[u] ? k.i : 0;
             const int cc[3] = {k.c.x, k.c.y, k.c.d};
 #pragma unroll
@@ -319,14 +340,14 @@ k_cut_ladder(Geo g, const float* __restrict__ xc, const float* __restrict__ w, P
     const int st[3] = {1, g.W, g.W * g.H};
     const int ext[3] = {g.W, g.H, g.D};
     Ladder L;
-    Walk k(g);
-    while (k.i < g.n) {
+    Walk k = xcd_walk(g);
+    while (k.i < k.end) {
         // loads of a group first (see kLadderGroup), then the voxels in walk order
         bool ok[kLadderGroup], he[kLadderGroup][ND];
         float xi[kLadderGroup], wv[kLadderGroup], xn[kLadderGroup][ND], av[kLadderGroup][ND], pv[kLadderGroup][ND];
 #pragma unroll
         for (int u = 0; u < kLadderGroup; ++u) {
-            ok[u] = k.i < g.n;
+            ok[u] = k.i < k.end;
             const int i = ok[u] ? k.i : 0;
             const int cc[3] = {k.c.x, k.c.y, k.c.d};
             xi[u] = xc[i];
@@ -721,7 +742,7 @@ hipError_t launch_cert(const Geo& g, const float* w, const float* const* a,
     }
     Taus tz;
     tau_ladder(tau0, tz.t);
-    const int nb = reduce_blocks(g.n);
+    const int nb = (reduce_blocks(g.n) + kXcds - 1) / kXcds * kXcds;  // <= kReduceBlocks
     double* part_lb = partials;
     double* part_cut = partials + kReduceBlocks;
     if (g.ndim == 3) {
