@@ -408,14 +408,59 @@ extern "C" int mc_tv_solve_batched(mc_ctx* c, int n_grids, const mc_grid* grids,
         for (const BatchGrid& t : host_tab) all_done = all_done && t.done;
         return MC_OK;
     };
-    while (it + K <= o.max_iters && !all_done) {
-        const hipError_t e = period();
-        if (e != hipSuccess) {
-            graph_err = hip_error(e, persistent ? "persistent batch launch" : "batch graph replay");
-            break;
+    if (persistent) {
+        while (it + K <= o.max_iters && !all_done) {
+            const hipError_t e = period();
+            if (e != hipSuccess) {
+                graph_err = hip_error(e, "persistent batch launch");
+                break;
+            }
+            it += K;
+            if ((graph_err = read_done())) break;
         }
-        it += K;
-        if ((graph_err = read_done())) break;
+    } else {
+        // Graph replays: each is followed by a count of the grids not done,
+        // copied to pinned memory behind an event of its own, and the host
+        // waits for a count only once the next replay is queued, so that the
+        // device does not idle while it reads.  Queuing never passes
+        // max_iters; behind the replay that finishes the last grid at most
+        // one more runs, in which the finished grids exit at once.
+        int* undone_dev = reinterpret_cast<int*>(c->bmeta + 128);
+        int* undone_h = reinterpret_cast<int*>(c->hout);
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        for (int k = 0; k < 2 && !graph_err; ++k) {
+            const hipError_t e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+            if (e != hipSuccess) graph_err = hip_error(e, "hipEventCreateWithFlags");
+        }
+        int queued = 0, wr = 0, rd = 0;
+        while (!graph_err && !all_done) {
+            while (queued < 2 && it + K <= o.max_iters) {
+                hipError_t e = period();
+                if (e == hipSuccess) e = launch_batch_undone(bl, undone_dev + wr, s);
+                if (e == hipSuccess)
+                    e = hipMemcpyAsync(undone_h + wr, undone_dev + wr, sizeof(int), hipMemcpyDeviceToHost, s);
+                if (e == hipSuccess) e = hipEventRecord(ev[wr], s);
+                if (e != hipSuccess) {
+                    graph_err = hip_error(e, "batch graph replay");
+                    break;
+                }
+                it += K;
+                wr ^= 1;
+                ++queued;
+            }
+            if (graph_err || queued == 0) break;
+            const hipError_t e = hipEventSynchronize(ev[rd]);
+            if (e != hipSuccess) {
+                graph_err = hip_error(e, "batch status wait");
+                break;
+            }
+            all_done = undone_h[rd] == 0;
+            rd ^= 1;
+            --queued;
+        }
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (!graph_err) graph_err = read_done();  // the table after the last replay
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);

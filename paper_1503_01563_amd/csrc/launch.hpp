@@ -210,6 +210,8 @@ hipError_t launch_batch_persistent(const BatchLaunch& b, int* ctl, int p0, int K
 hipError_t launch_batch_check(const BatchLaunch& b, float tau0, double gap_tol, const int* iter_dev,
                               double* partials, hipStream_t s);
 hipError_t launch_batch_labels(const BatchLaunch& b, float tau0, hipStream_t s);
+// The number of grids whose done flag is not set, to *out (device).
+hipError_t launch_batch_undone(const BatchLaunch& b, int* out, hipStream_t s);
 hipError_t launch_set_int(int* dst, int value, hipStream_t s);
 hipError_t launch_stamp(unsigned long long* dst, hipStream_t s);
 

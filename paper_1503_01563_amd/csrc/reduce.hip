@@ -579,6 +579,16 @@ k_batch_finalize(BatchLaunch b, const double* __restrict__ partials, double gap_
     }
 }
 
+// number of grids of a batch not finished yet (one wave)
+__global__ void __launch_bounds__(64) k_batch_undone(BatchLaunch b, int* __restrict__ out)
+{
+    int c = 0;
+    for (int g = threadIdx.x; g < b.n_grids; g += 64) c += b.tab[g].done ? 0 : 1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (threadIdx.x == 0) *out = c;
+}
+
 __global__ void __launch_bounds__(kReduceThreads) k_batch_labels(BatchLaunch b, Taus tz)
 {
     const BatchGrid& t = b.tab[b.blk_grid[blockIdx.x]];
@@ -812,6 +822,12 @@ hipError_t launch_batch_check(const BatchLaunch& b, float tau0, double gap_tol, 
     hipLaunchKernelGGL(k_batch_cut, dim3(b.blocks), dim3(kReduceThreads), 0, s, b, tz, partials);
     hipLaunchKernelGGL(k_batch_finalize, dim3(b.n_grids), dim3(kReduceThreads), 0, s, b, partials,
                        gap_tol, iter_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_undone(const BatchLaunch& b, int* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_undone, dim3(1), dim3(64), 0, s, b, out);
     return hipGetLastError();
 }
 
